@@ -1,0 +1,761 @@
+// Host side of the lbmve C ABI: parameter validation, workspace layout,
+// tile tables, HIP-graph step replays, observables, export / import.
+//
+// A single run is a batch of one: every entry point below drives the same
+// tile-table kernels, so a run advanced alone and the same run advanced
+// inside any batch produce bit-identical fields.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/lbmve.h"
+#include "lbm_internal.h"
+
+using lbm::RunDev;
+using lbm::Tile;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int MAX_TARGETS = 64;
+constexpr int GRAPH_CHUNKS[4] = {64, 16, 4, 1};
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Targets {
+  int32_t target[MAX_TARGETS];
+  int32_t base[MAX_TARGETS];
+};
+
+__global__ void k_set_targets(RunDev* runs, int32_t first, int32_t count, Targets t, int32_t* gstep) {
+  const int i = threadIdx.x;
+  if (i < count) {
+    runs[first + i].target = t.target[i];
+    runs[first + i].base = t.base[i];
+  }
+  if (i == 0 && first == 0) *gstep = 0;
+}
+
+// Mean-field coexistence mass fractions of the symmetric Shan-Chen mixture
+// (psi = rho, unit-sum interaction weights): atanh(m) = (3/2) G rho_tot m;
+// returns false when G rho_tot <= 2/3 (no demixing).
+bool coexistence(double G, double rho_tot, double* lo, double* hi) {
+  const double k = 1.5 * G * rho_tot;
+  if (k <= 1.0) return false;
+  double a = 0.0, b = 1.0;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (a + b);
+    if (mid <= 0.0 || mid >= 1.0) break;
+    if (std::atanh(mid) - k * mid > 0.0) b = mid; else a = mid;
+  }
+  const double m = 0.5 * (a + b);
+  *lo = 0.5 * (1.0 - m);
+  *hi = 0.5 * (1.0 + m);
+  return true;
+}
+
+struct Layout {
+  size_t f[2], rho[2], j[2], C[2], recA, recB, u, labels, counts, status, ncomp, gstep,
+      runs, tiles, partials, obs, rc, rinit, total;
+  int64_t tiles_cap;
+};
+
+size_t elem_S(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2); }
+size_t elem_T(int prec) { return prec == LBM_FP64 ? 8 : 4; }
+
+int64_t max_tiles(const lbm_params* p, int32_t nruns) {
+  // smallest tile: bx = 32, by = 1, bz = 1
+  int64_t t = 0;
+  for (int r = 0; r < nruns; ++r) t += (int64_t)((p[r].nx + 31) / 32) * p[r].ny * p[r].nz;
+  return (t + 7) / 8 * 8;
+}
+
+Layout make_layout(const lbm_params* p, int32_t nruns) {
+  Layout L{};
+  int64_t nodes = 0;
+  for (int r = 0; r < nruns; ++r) nodes += (int64_t)p[r].nx * p[r].ny * p[r].nz;
+  const int prec = p[0].precision;
+  const size_t s = elem_S(prec), t = elem_T(prec);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes); return o; };
+  for (int b = 0; b < 2; ++b) L.f[b] = take((size_t)nodes * 38 * s);
+  for (int b = 0; b < 2; ++b) L.rho[b] = take((size_t)nodes * 2 * t);
+  for (int b = 0; b < 2; ++b) L.j[b] = take((size_t)nodes * 6 * t);
+  for (int b = 0; b < 2; ++b) L.C[b] = take((size_t)nodes * 6 * t);
+  L.recA = take((size_t)nodes * 4 * t);
+  L.recB = take((size_t)nodes * 4 * t);
+  L.u = take((size_t)nodes * 3 * t);
+  L.labels = take((size_t)nodes * 4);
+  L.counts = take((size_t)nodes * 4);
+  L.status = take((size_t)nruns * 4);
+  L.ncomp = take((size_t)nruns * 4);
+  L.gstep = take(4);
+  L.runs = take((size_t)nruns * sizeof(RunDev));
+  L.tiles_cap = max_tiles(p, nruns);
+  L.tiles = take((size_t)L.tiles_cap * sizeof(Tile));
+  L.partials = take((size_t)nruns * lbm::AUX_BLOCKS * lbm::NOBS * 8);
+  L.obs = take((size_t)nruns * lbm::NOBS * 8);
+  L.rc = take((size_t)nruns * 4 * 8);
+  L.rinit = take((size_t)nruns * 2 * 8);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  int32_t nruns = 0, prec = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  std::vector<lbm_params> prm;
+  std::vector<RunDev> runs;
+  std::vector<int64_t> done;
+  char* ws = nullptr;
+  Layout L{};
+  lbm_launch launch{64, 4, 1, 0};
+  int64_t ntiles = 0;          // entries of the (XCD-permuted) tile table
+  std::map<int, hipGraphExec_t> graphs;
+  std::map<int, hipGraph_t> graph_src;
+
+  template <typename P>
+  P* at(size_t o) const { return reinterpret_cast<P*>(ws + o); }
+};
+
+namespace {
+
+template <typename T, typename S>
+lbm::Pools<T, S> pools(const lbm_ctx* c) {
+  lbm::Pools<T, S> P;
+  for (int b = 0; b < 2; ++b) {
+    P.f[b] = c->at<S>(c->L.f[b]);
+    P.rho[b] = c->at<lbm::V2<T>>(c->L.rho[b]);
+    P.j[b] = c->at<T>(c->L.j[b]);
+    P.C[b] = c->at<T>(c->L.C[b]);
+  }
+  P.recA = c->at<lbm::V4<T>>(c->L.recA);
+  P.recB = c->at<lbm::V4<T>>(c->L.recB);
+  P.u = c->at<T>(c->L.u);
+  P.status = c->at<uint32_t>(c->L.status);
+  return P;
+}
+
+template <typename T, typename S>
+lbm::StepArgs<T, S> step_args(const lbm_ctx* c) {
+  lbm::StepArgs<T, S> a;
+  a.P = pools<T, S>(c);
+  a.runs = c->at<RunDev>(c->L.runs);
+  a.tiles = c->at<Tile>(c->L.tiles);
+  a.ntiles = (int32_t)c->ntiles;
+  a.bz = c->launch.bz;
+  a.gstep = c->at<int32_t>(c->L.gstep);
+  return a;
+}
+
+template <typename T, typename S>
+lbm::AuxArgs<T, S> aux_args(const lbm_ctx* c, int use_parity) {
+  lbm::AuxArgs<T, S> a;
+  a.P = pools<T, S>(c);
+  a.runs = c->at<RunDev>(c->L.runs);
+  a.nruns = c->nruns;
+  a.use_parity = use_parity;
+  a.partials = c->at<double>(c->L.partials);
+  a.obs = c->at<double>(c->L.obs);
+  a.labels = c->at<int32_t>(c->L.labels);
+  a.counts = c->at<int32_t>(c->L.counts);
+  a.ncomp = c->at<int32_t>(c->L.ncomp);
+  a.radius_centre = c->at<double>(c->L.rc);
+  a.rho_init = c->at<double>(c->L.rinit);
+  return a;
+}
+
+dim3 step_grid(const lbm_ctx* c) {
+  int64_t g = c->ntiles;
+  if (c->launch.persistent > 0) g = std::min<int64_t>(g, std::max(8, c->launch.persistent / 8 * 8));
+  return dim3((unsigned)g);
+}
+
+// Dispatch on precision: F is a generic lambda taking (T*, S*) tags.
+template <typename F>
+void by_precision(int prec, F&& fn) {
+  if (prec == LBM_FP64) fn((double*)nullptr, (double*)nullptr);
+  else if (prec == LBM_FP32) fn((float*)nullptr, (float*)nullptr);
+  else fn((float*)nullptr, (__half*)nullptr);
+}
+
+int hip_ok(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
+#define HIPCHK(x) do { if ((x) != hipSuccess) return LBM_EHIP; } while (0)
+
+int validate(const lbm_params* p) {
+  if (!p) return LBM_EINVAL;
+  if (p->nx < 3 || p->ny < 3 || p->nz < 3) return LBM_EINVAL;
+  const int64_t n = (int64_t)p->nx * p->ny * p->nz;
+  if (n >= (int64_t)1 << 31) return LBM_EINVAL;
+  if (p->precision < LBM_FP64 || p->precision > LBM_FP16S) return LBM_EINVAL;
+  if (!(std::fabs(p->u_wall) < 0.2)) return LBM_EINVAL;
+  if (!(p->radius >= 0.0) || !(p->radius < 0.5 * p->nz)) return LBM_EINVAL;
+  if (!(p->rho_major > 0.0) || !(p->rho_minor > 0.0)) return LBM_EINVAL;
+  if (!(p->G >= 0.0) || !std::isfinite(p->G)) return LBM_EINVAL;
+  for (int s = 0; s < 2; ++s) {
+    if (!(p->tau[s] > 0.5) || !std::isfinite(p->tau[s])) return LBM_EINVAL;
+    if (!(p->eta_P[s] >= 0.0) || !std::isfinite(p->eta_P[s])) return LBM_EINVAL;
+    if (!(p->rho0[s] >= 0.0) || !std::isfinite(p->rho0[s])) return LBM_EINVAL;
+    if (p->eta_P[s] > 0.0) {
+      if (!(p->tau_P[s] > 0.0) || !std::isfinite(p->tau_P[s])) return LBM_EINVAL;
+      if (!(p->L2[s] > 3.0)) return LBM_EINVAL;
+    }
+  }
+  if (p->eta_P[0] > 0.0 && p->eta_P[1] > 0.0) return LBM_EINVAL;
+  if (!(p->chi_lo == 0.0 && p->chi_hi == 0.0)) {
+    if (!(p->chi_hi > p->chi_lo) || !std::isfinite(p->chi_lo) || !std::isfinite(p->chi_hi))
+      return LBM_EINVAL;
+  }
+  if (!std::isfinite(p->cx) || !std::isfinite(p->cy) || !std::isfinite(p->cz)) return LBM_EINVAL;
+  return LBM_OK;
+}
+
+int validate_all(const lbm_params* runs, int32_t nruns) {
+  if (!runs || nruns < 1) return LBM_EINVAL;
+  for (int r = 0; r < nruns; ++r) {
+    const int e = validate(runs + r);
+    if (e) return e;
+    if (runs[r].precision != runs[0].precision) return LBM_EINVAL;
+  }
+  return LBM_OK;
+}
+
+RunDev make_run(const lbm_params& p, int64_t off) {
+  RunDev R{};
+  R.nx = p.nx; R.ny = p.ny; R.nz = p.nz;
+  R.visc = p.eta_P[0] > 0.0 ? 0 : (p.eta_P[1] > 0.0 ? 1 : -1);
+  R.n = (int64_t)p.nx * p.ny * p.nz;
+  R.off = off;
+  R.target = 0;
+  R.base = 0;
+  R.u_wall = p.u_wall;
+  R.G = p.G;
+  for (int s = 0; s < 2; ++s) {
+    R.tau[s] = p.tau[s];
+    R.inv_tau[s] = 1.0 / p.tau[s];
+    R.rho0[s] = p.precision == LBM_FP16S ? (p.rho0[s] > 0.0 ? p.rho0[s] : p.rho_major) : 0.0;
+  }
+  if (R.visc >= 0) {
+    const int v = R.visc;
+    R.inv_tauP = 1.0 / p.tau_P[v];
+    R.etaP_over_tauP = p.eta_P[v] / p.tau_P[v];
+    R.L2 = p.L2[v];
+  } else {
+    R.inv_tauP = 0.0; R.etaP_over_tauP = 0.0; R.L2 = 1e300;
+  }
+  double lo = p.chi_lo, hi = p.chi_hi;
+  if (lo == 0.0 && hi == 0.0) {
+    const double rt = p.rho_major + p.rho_minor;
+    if (!coexistence(p.G, rt, &lo, &hi)) { lo = p.rho_minor / rt; hi = p.rho_major / rt; }
+  }
+  R.chi_lo = lo;
+  R.inv_chi_range = 1.0 / (hi - lo);
+  // smallest droplet piece counted: 1% of the initial droplet volume
+  const double cx = p.cx < 0 ? 0.5 * (p.nx - 1) : p.cx;
+  const double cy = p.cx < 0 ? 0.5 * (p.ny - 1) : p.cy;
+  const double cz = p.cx < 0 ? 0.5 * (p.nz - 1) : p.cz;
+  int64_t inside = 0;
+  for (int z = 0; z < p.nz; ++z)
+    for (int y = 0; y < p.ny; ++y)
+      for (int x = 0; x < p.nx; ++x) {
+        const double dx = x - cx, dy = y - cy, dz = z - cz;
+        inside += dx * dx + dy * dy + dz * dz < p.radius * p.radius;
+      }
+  R.min_cc = (int32_t)std::max<int64_t>(1, (inside + 99) / 100);
+  return R;
+}
+
+void destroy_graphs(lbm_ctx* c) {
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  for (auto& kv : c->graph_src) hipGraphDestroy(kv.second);
+  c->graphs.clear();
+  c->graph_src.clear();
+}
+
+// Tile table: canonical order (run, tz, ty, tx), then permuted so that the
+// workgroups one XCD receives (dispatch is round-robin over the 8 XCDs) own a
+// contiguous block of tiles and share halo rows in that XCD's L2.
+int build_tiles(lbm_ctx* c) {
+  const lbm_launch& l = c->launch;
+  std::vector<Tile> canon;
+  for (int r = 0; r < c->nruns; ++r) {
+    const RunDev& R = c->runs[r];
+    for (int z = 0; z < R.nz; z += l.bz)
+      for (int y = 0; y < R.ny; y += l.by)
+        for (int x = 0; x < R.nx; x += l.bx) canon.push_back(Tile{r, x, y, z});
+  }
+  const int64_t T = (int64_t)canon.size();
+  const int64_t Tp = (T + 7) / 8 * 8;
+  if (Tp > c->L.tiles_cap) return LBM_EINVAL;
+  std::vector<Tile> table(Tp);
+  const int64_t per = Tp / 8;
+  for (int64_t p = 0; p < Tp; ++p) {
+    const int64_t cidx = (p % 8) * per + p / 8;
+    table[p] = cidx < T ? canon[cidx] : Tile{-1, 0, 0, 0};
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(c->at<Tile>(c->L.tiles), table.data(), Tp * sizeof(Tile), hipMemcpyHostToDevice));
+  c->ntiles = Tp;
+  destroy_graphs(c);
+  return LBM_OK;
+}
+
+// Enqueue the per-run step targets and reset the device step counter.
+int set_targets(lbm_ctx* c, const int32_t* target) {
+  for (int first = 0; first < c->nruns; first += MAX_TARGETS) {
+    const int count = std::min(MAX_TARGETS, c->nruns - first);
+    Targets t{};
+    for (int i = 0; i < count; ++i) {
+      t.target[i] = target[first + i];
+      t.base[i] = (int32_t)(c->done[first + i] & 1);
+      c->runs[first + i].target = t.target[i];
+      c->runs[first + i].base = t.base[i];
+    }
+    k_set_targets<<<1, MAX_TARGETS, 0, c->stream>>>(c->at<RunDev>(c->L.runs), first, count, t,
+                                                    c->at<int32_t>(c->L.gstep));
+  }
+  return hip_ok(hipGetLastError());
+}
+
+void enqueue_force(lbm_ctx* c, hipStream_t s) {
+  const dim3 grid = step_grid(c), block(c->launch.bx, c->launch.by);
+  by_precision(c->prec, [&](auto* tt, auto* ss) {
+    using T = std::remove_pointer_t<decltype(tt)>;
+    using S = std::remove_pointer_t<decltype(ss)>;
+    lbm::launch_force<T, S>(step_args<T, S>(c), grid, block, s);
+  });
+}
+
+void enqueue_step(lbm_ctx* c, hipStream_t s) {
+  const dim3 grid = step_grid(c), block(c->launch.bx, c->launch.by);
+  by_precision(c->prec, [&](auto* tt, auto* ss) {
+    using T = std::remove_pointer_t<decltype(tt)>;
+    using S = std::remove_pointer_t<decltype(ss)>;
+    const auto a = step_args<T, S>(c);
+    lbm::launch_force<T, S>(a, grid, block, s);
+    lbm::launch_update<T, S>(a, grid, block, s);
+  });
+  lbm::launch_inc_step(c->at<int32_t>(c->L.gstep), s);
+}
+
+int get_graph(lbm_ctx* c, int chunk, hipGraphExec_t* out) {
+  auto it = c->graphs.find(chunk);
+  if (it != c->graphs.end()) { *out = it->second; return LBM_OK; }
+  if (!c->cap) HIPCHK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < chunk; ++k) enqueue_step(c, c->cap);
+  const hipError_t e = hipStreamEndCapture(c->cap, &g);
+  if (e != hipSuccess || !g) return LBM_EHIP;
+  hipGraphExec_t ex = nullptr;
+  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(g);
+    return LBM_EHIP;
+  }
+  c->graph_src[chunk] = g;
+  c->graphs[chunk] = ex;
+  *out = ex;
+  return LBM_OK;
+}
+
+int run_steps(lbm_ctx* c, const int32_t* target) {
+  int32_t m = 0;
+  for (int r = 0; r < c->nruns; ++r) {
+    if (target[r] < 0) return LBM_EINVAL;
+    m = std::max(m, target[r]);
+  }
+  if (m == 0) return LBM_OK;
+  int e = set_targets(c, target);
+  if (e) return e;
+  int remaining = m;
+  for (int chunk : GRAPH_CHUNKS) {
+    while (remaining >= chunk) {
+      hipGraphExec_t ex;
+      e = get_graph(c, chunk, &ex);
+      if (e) return e;
+      HIPCHK(hipGraphLaunch(ex, c->stream));
+      remaining -= chunk;
+    }
+  }
+  for (int r = 0; r < c->nruns; ++r) c->done[r] += target[r];
+  return LBM_OK;
+}
+
+// Force pass on the current state of every run (fills u^eq and u).
+int refresh_flow(lbm_ctx* c) {
+  std::vector<int32_t> one(c->nruns, 1);
+  const int e = set_targets(c, one.data());
+  if (e) return e;
+  enqueue_force(c, c->stream);
+  return hip_ok(hipGetLastError());
+}
+
+void finish_obs(const lbm_ctx* c, int r, const double* o, lbm_obs* out) {
+  const lbm_params& p = c->prm[r];
+  std::memset(out, 0, sizeof(*out));
+  out->step = c->done[r];
+  out->mass[0] = o[lbm::OB_MA];
+  out->mass[1] = o[lbm::OB_MB];
+  const double W = o[lbm::OB_W];
+  out->weight = W;
+  const double hx = 0.5 * (p.nx - 1), hy = 0.5 * (p.ny - 1), hz = 0.5 * (p.nz - 1);
+  if (W > 0.0) {
+    const double X = o[lbm::OB_WX] / W, Y = o[lbm::OB_WY] / W, Z = o[lbm::OB_WZ] / W;
+    const double Ixx = o[lbm::OB_WXX] - W * X * X;
+    const double Ixz = o[lbm::OB_WXZ] - W * X * Z;
+    const double Izz = o[lbm::OB_WZZ] - W * Z * Z;
+    out->centroid[0] = X + hx; out->centroid[1] = Y + hy; out->centroid[2] = Z + hz;
+    out->inertia[0] = Ixx; out->inertia[1] = Ixz; out->inertia[2] = Izz;
+    const double mean = 0.5 * (Ixx + Izz);
+    const double rad = std::sqrt(0.25 * (Ixx - Izz) * (Ixx - Izz) + Ixz * Ixz);
+    const double lp = mean + rad, lm = std::max(mean - rad, 0.0);
+    const double sp = std::sqrt(lp), sm = std::sqrt(lm);
+    out->D = sp + sm > 0.0 ? (sp - sm) / (sp + sm) : 0.0;
+    out->theta_deg = 0.5 * std::atan2(2.0 * Ixz, Ixx - Izz) * (180.0 / M_PI);
+  }
+  out->Lp = o[lbm::OB_XMAX] >= o[lbm::OB_XMIN] ? o[lbm::OB_XMAX] - o[lbm::OB_XMIN] + 1.0 : 0.0;
+  out->umax = std::sqrt(o[lbm::OB_U2MAX]);
+  out->trC_max = o[lbm::OB_TRCMAX];
+  out->n_components = -1;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char* lbm_strerror(int code) {
+  switch (code) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "workspace too small";
+    case LBM_EHIP: return "HIP runtime error";
+    case LBM_EUNSUP: return "unsupported device or combination";
+    case LBM_ENAN: return "non-finite value in the state";
+    case LBM_EFENE: return "conformation trace reached L^2";
+    default: return "unknown status";
+  }
+}
+
+int lbm_validate(const lbm_params* p) { return validate(p); }
+
+int lbm_batch_workspace_bytes(const lbm_params* runs, int32_t nruns, size_t* bytes) {
+  if (!bytes) return LBM_EINVAL;
+  const int e = validate_all(runs, nruns);
+  if (e) return e;
+  *bytes = make_layout(runs, nruns).total;
+  return LBM_OK;
+}
+
+int lbm_workspace_bytes(const lbm_params* p, size_t* bytes) { return lbm_batch_workspace_bytes(p, 1, bytes); }
+
+int lbm_batch_init(const lbm_params* runs, int32_t nruns, void* ws, size_t bytes, void* stream,
+                   lbm_ctx** out) {
+  if (!out || !ws) return LBM_EINVAL;
+  *out = nullptr;
+  int e = validate_all(runs, nruns);
+  if (e) return e;
+  const Layout L = make_layout(runs, nruns);
+  if (bytes < L.total) return LBM_ENOMEM;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return LBM_EUNSUP;
+
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_EINVAL;
+  c->nruns = nruns;
+  c->prec = runs[0].precision;
+  c->stream = (hipStream_t)stream;
+  c->ws = (char*)ws;
+  c->L = L;
+  c->prm.assign(runs, runs + nruns);
+  c->done.assign(nruns, 0);
+  int64_t off = 0;
+  std::vector<double> rc(4 * nruns), rinit(2 * nruns);
+  for (int r = 0; r < nruns; ++r) {
+    c->runs.push_back(make_run(runs[r], off));
+    off += c->runs.back().n;
+    const lbm_params& p = runs[r];
+    const bool centre = p.cx < 0;
+    rc[4 * r] = p.radius;
+    rc[4 * r + 1] = centre ? 0.5 * (p.nx - 1) : p.cx;
+    rc[4 * r + 2] = centre ? 0.5 * (p.ny - 1) : p.cy;
+    rc[4 * r + 3] = centre ? 0.5 * (p.nz - 1) : p.cz;
+    rinit[2 * r] = p.rho_major;
+    rinit[2 * r + 1] = p.rho_minor;
+  }
+  auto fail = [&](int code) { lbm_destroy(c); return code; };
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(LBM_EHIP);
+  if (hipMemcpy(c->at<RunDev>(L.runs), c->runs.data(), nruns * sizeof(RunDev), hipMemcpyHostToDevice) ||
+      hipMemcpy(c->at<double>(L.rc), rc.data(), rc.size() * 8, hipMemcpyHostToDevice) ||
+      hipMemcpy(c->at<double>(L.rinit), rinit.data(), rinit.size() * 8, hipMemcpyHostToDevice))
+    return fail(LBM_EHIP);
+  e = build_tiles(c);
+  if (e) return fail(e);
+  lbm::launch_fill_u32(c->at<uint32_t>(L.status), 0u, nruns, c->stream);
+  by_precision(c->prec, [&](auto* tt, auto* ss) {
+    using T = std::remove_pointer_t<decltype(tt)>;
+    using S = std::remove_pointer_t<decltype(ss)>;
+    const auto a = aux_args<T, S>(c, 0);
+    lbm::launch_init<T, S>(a, c->stream);
+    lbm::launch_moments<T, S>(a, c->stream);
+  });
+  if (hipGetLastError() != hipSuccess) return fail(LBM_EHIP);
+  *out = c;
+  return LBM_OK;
+}
+
+int lbm_init(const lbm_params* p, void* ws, size_t bytes, void* stream, lbm_ctx** out) {
+  return lbm_batch_init(p, 1, ws, bytes, stream, out);
+}
+
+void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  if (c->stream || c->cap) hipStreamSynchronize(c->stream);
+  destroy_graphs(c);
+  if (c->cap) hipStreamDestroy(c->cap);
+  delete c;
+}
+
+int32_t lbm_batch_nruns(const lbm_ctx* c) { return c ? c->nruns : 0; }
+
+int lbm_get_launch(const lbm_ctx* c, lbm_launch* out) {
+  if (!c || !out) return LBM_EINVAL;
+  *out = c->launch;
+  return LBM_OK;
+}
+
+int lbm_set_launch(lbm_ctx* c, const lbm_launch* in) {
+  if (!c || !in) return LBM_EINVAL;
+  const lbm_launch l = *in;
+  const bool bx_ok = l.bx == 32 || l.bx == 64 || l.bx == 128 || l.bx == 256;
+  const bool by_ok = l.by == 1 || l.by == 2 || l.by == 4 || l.by == 8;
+  if (!bx_ok || !by_ok || l.bx * l.by > 256 || l.bz < 1 || l.bz > 16 || l.persistent < 0)
+    return LBM_EINVAL;
+  const lbm_launch old = c->launch;
+  c->launch = l;
+  const int e = build_tiles(c);
+  if (e) { c->launch = old; build_tiles(c); }
+  return e;
+}
+
+int lbm_steps_done(const lbm_ctx* c, int32_t run, int64_t* out) {
+  if (!c || !out || run < 0 || run >= c->nruns) return LBM_EINVAL;
+  *out = c->done[run];
+  return LBM_OK;
+}
+
+int lbm_batch_step(lbm_ctx* c, const int32_t* steps) {
+  if (!c || !steps) return LBM_EINVAL;
+  return run_steps(c, steps);
+}
+
+int lbm_step_profiled(lbm_ctx* c, int32_t nsteps, double* ms_pass) {
+  if (!c || nsteps < 0 || !ms_pass) return LBM_EINVAL;
+  ms_pass[0] = ms_pass[1] = 0.0;
+  if (nsteps == 0) return LBM_OK;
+  std::vector<int32_t> t(c->nruns, nsteps);
+  int e = set_targets(c, t.data());
+  if (e) return e;
+  std::vector<hipEvent_t> ev(3 * (size_t)nsteps, nullptr);
+  for (auto& x : ev)
+    if (hipEventCreate(&x) != hipSuccess) { e = LBM_EHIP; break; }
+  const dim3 grid = step_grid(c), block(c->launch.bx, c->launch.by);
+  for (int k = 0; k < nsteps && !e; ++k) {
+    by_precision(c->prec, [&](auto* tt, auto* ss) {
+      using T = std::remove_pointer_t<decltype(tt)>;
+      using S = std::remove_pointer_t<decltype(ss)>;
+      const auto a = step_args<T, S>(c);
+      hipEventRecord(ev[3 * k], c->stream);
+      lbm::launch_force<T, S>(a, grid, block, c->stream);
+      hipEventRecord(ev[3 * k + 1], c->stream);
+      lbm::launch_update<T, S>(a, grid, block, c->stream);
+      hipEventRecord(ev[3 * k + 2], c->stream);
+    });
+    lbm::launch_inc_step(c->at<int32_t>(c->L.gstep), c->stream);
+  }
+  if (!e && hipStreamSynchronize(c->stream) != hipSuccess) e = LBM_EHIP;
+  for (int k = 0; k < nsteps && !e; ++k) {
+    float a = 0.f, b = 0.f;
+    if (hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]) != hipSuccess ||
+        hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]) != hipSuccess) { e = LBM_EHIP; break; }
+    ms_pass[0] += a;
+    ms_pass[1] += b;
+  }
+  for (auto& x : ev)
+    if (x) hipEventDestroy(x);
+  if (e) return e;
+  for (int r = 0; r < c->nruns; ++r) c->done[r] += nsteps;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int32_t nsteps) {
+  if (!c || nsteps < 0) return LBM_EINVAL;
+  std::vector<int32_t> t(c->nruns, nsteps);
+  return run_steps(c, t.data());
+}
+
+int lbm_batch_observe(lbm_ctx* c, int32_t want_cc, lbm_obs* out) {
+  if (!c || !out) return LBM_EINVAL;
+  int e = refresh_flow(c);
+  if (e) return e;
+  by_precision(c->prec, [&](auto* tt, auto* ss) {
+    using T = std::remove_pointer_t<decltype(tt)>;
+    using S = std::remove_pointer_t<decltype(ss)>;
+    const auto a = aux_args<T, S>(c, 1);
+    lbm::launch_observe<T, S>(a, c->stream);
+    if (want_cc) lbm::launch_components<T, S>(a, c->stream);
+  });
+  HIPCHK(hipGetLastError());
+  std::vector<double> o((size_t)c->nruns * lbm::NOBS);
+  std::vector<uint32_t> st(c->nruns);
+  std::vector<int32_t> nc(c->nruns);
+  HIPCHK(hipMemcpyAsync(o.data(), c->at<double>(c->L.obs), o.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(st.data(), c->at<uint32_t>(c->L.status), st.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(nc.data(), c->at<int32_t>(c->L.ncomp), nc.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  int first = LBM_OK;
+  for (int r = 0; r < c->nruns; ++r) {
+    finish_obs(c, r, o.data() + (size_t)r * lbm::NOBS, out + r);
+    if (want_cc) out[r].n_components = nc[r];
+    int s = LBM_OK;
+    if ((st[r] & lbm::ST_NAN) || o[(size_t)r * lbm::NOBS + lbm::OB_NONFINITE] > 0) s = LBM_ENAN;
+    else if (st[r] & lbm::ST_FENE) s = LBM_EFENE;
+    else if (want_cc && (st[r] & lbm::ST_CC)) s = LBM_EHIP;
+    out[r].status = s;
+    if (s && !first) first = s;
+  }
+  return first;
+}
+
+int lbm_observe(lbm_ctx* c, int32_t want_cc, lbm_obs* out) {
+  if (!c || !out) return LBM_EINVAL;
+  std::vector<lbm_obs> all(c->nruns);
+  const int e = lbm_batch_observe(c, want_cc, all.data());
+  *out = all[0];
+  return e == LBM_EINVAL || e == LBM_EHIP ? e : all[0].status;
+}
+
+static int64_t field_elems(const lbm_params& p, int field) {
+  const int64_t n = (int64_t)p.nx * p.ny * p.nz;
+  switch (field) {
+    case LBM_FIELD_F: return 38 * n;
+    case LBM_FIELD_C: return 6 * n;
+    case LBM_FIELD_RHO: return 2 * n;
+    case LBM_FIELD_U: return 3 * n;
+    default: return -1;
+  }
+}
+
+int lbm_batch_export(lbm_ctx* c, int32_t run, int32_t field, double* host, size_t n) {
+  if (!c || !host || run < 0 || run >= c->nruns) return LBM_EINVAL;
+  const int64_t want = field_elems(c->prm[run], field);
+  if (want < 0 || (int64_t)n != want) return LBM_EINVAL;
+  const RunDev& R = c->runs[run];
+  const int par = (int)(c->done[run] & 1);
+  const int64_t N = R.n;
+  if (field == LBM_FIELD_U) {
+    const int e = refresh_flow(c);
+    if (e) return e;
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const size_t st = elem_S(c->prec), tt = elem_T(c->prec);
+  std::vector<char> buf;
+  if (field == LBM_FIELD_F) {
+    buf.resize((size_t)want * st);
+    HIPCHK(hipMemcpy(buf.data(), c->ws + c->L.f[par] + (size_t)R.off * 38 * st, buf.size(), hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < want; ++k) {
+      if (c->prec == LBM_FP64) host[k] = ((double*)buf.data())[k];
+      else if (c->prec == LBM_FP32) host[k] = ((float*)buf.data())[k];
+      else {
+        const int s = (int)(k / (19 * N)), i = (int)((k / N) % 19);
+        const float shift = lbm::wgt<float>(i) * (float)R.rho0[s];
+        host[k] = (double)(__half2float(((__half*)buf.data())[k]) + shift);
+      }
+    }
+    return LBM_OK;
+  }
+  size_t src = 0;
+  if (field == LBM_FIELD_C) src = c->L.C[R.visc >= 0 ? par : 0] + (size_t)R.off * 6 * tt;
+  else if (field == LBM_FIELD_RHO) src = c->L.rho[par] + (size_t)R.off * 2 * tt;
+  else src = c->L.u + (size_t)R.off * 3 * tt;
+  buf.resize((size_t)want * tt);
+  HIPCHK(hipMemcpy(buf.data(), c->ws + src, buf.size(), hipMemcpyDeviceToHost));
+  for (int64_t k = 0; k < want; ++k) {
+    const double v = tt == 8 ? ((double*)buf.data())[k] : (double)((float*)buf.data())[k];
+    if (field == LBM_FIELD_RHO) {
+      // device layout (rho_A, rho_B) per node -> [2][N]
+      const int64_t node = k / 2, comp = k % 2;
+      host[comp * N + node] = v;
+    } else {
+      host[k] = v;
+    }
+  }
+  return LBM_OK;
+}
+
+int lbm_export(lbm_ctx* c, int32_t field, double* host, size_t n) {
+  return lbm_batch_export(c, 0, field, host, n);
+}
+
+int lbm_batch_import(lbm_ctx* c, int32_t run, int32_t field, const double* host, size_t n) {
+  if (!c || !host || run < 0 || run >= c->nruns) return LBM_EINVAL;
+  if (field != LBM_FIELD_F && field != LBM_FIELD_C) return LBM_EINVAL;
+  const int64_t want = field_elems(c->prm[run], field);
+  if ((int64_t)n != want) return LBM_EINVAL;
+  const RunDev& R = c->runs[run];
+  const int par = (int)(c->done[run] & 1);
+  const int64_t N = R.n;
+  const size_t st = elem_S(c->prec), tt = elem_T(c->prec);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::vector<char> buf;
+  if (field == LBM_FIELD_F) {
+    buf.resize((size_t)want * st);
+    for (int64_t k = 0; k < want; ++k) {
+      if (c->prec == LBM_FP64) ((double*)buf.data())[k] = host[k];
+      else if (c->prec == LBM_FP32) ((float*)buf.data())[k] = (float)host[k];
+      else {
+        const int s = (int)(k / (19 * N)), i = (int)((k / N) % 19);
+        const float shift = lbm::wgt<float>(i) * (float)R.rho0[s];
+        ((__half*)buf.data())[k] = __float2half_rn((float)host[k] - shift);
+      }
+    }
+    HIPCHK(hipMemcpy(c->ws + c->L.f[par] + (size_t)R.off * 38 * st, buf.data(), buf.size(), hipMemcpyHostToDevice));
+  } else {
+    buf.resize((size_t)want * tt);
+    for (int64_t k = 0; k < want; ++k) {
+      if (tt == 8) ((double*)buf.data())[k] = host[k];
+      else ((float*)buf.data())[k] = (float)host[k];
+    }
+    // a Newtonian run never updates C, which stays at parity 0
+    const int cp = R.visc >= 0 ? par : 0;
+    HIPCHK(hipMemcpy(c->ws + c->L.C[cp] + (size_t)R.off * 6 * tt, buf.data(), buf.size(), hipMemcpyHostToDevice));
+  }
+  // moments of every run at its current parity; clear this run's status
+  std::vector<int32_t> zero(c->nruns, 0);
+  int e = set_targets(c, zero.data());
+  if (e) return e;
+  by_precision(c->prec, [&](auto* ttag, auto* stag) {
+    using T = std::remove_pointer_t<decltype(ttag)>;
+    using S = std::remove_pointer_t<decltype(stag)>;
+    lbm::launch_moments<T, S>(aux_args<T, S>(c, 1), c->stream);
+  });
+  lbm::launch_fill_u32(c->at<uint32_t>(c->L.status) + run, 0u, 1, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_import(lbm_ctx* c, int32_t field, const double* host, size_t n) {
+  return lbm_batch_import(c, 0, field, host, n);
+}
+
+}  // extern "C"

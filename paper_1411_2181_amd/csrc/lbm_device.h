@@ -1,0 +1,104 @@
+// Device-side definitions shared by the lbmve kernels: the D3Q19 tables as
+// compile-time constants, the per-run parameter record, the tile record and
+// the storage conversions of the three precisions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// ---- D3Q19 (direction order documented in include/lbmve.h) -------------
+constexpr int Q = 19;
+constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr int OPPI[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+// weight classes: 0 rest (1/3), 1 axis (1/18), 2 diagonal (1/36)
+constexpr int WCLASS[Q] = {0, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2};
+
+template <typename T>
+__host__ __device__ constexpr T wgt(int i) {
+  return WCLASS[i] == 0 ? T(1) / T(3) : (WCLASS[i] == 1 ? T(1) / T(18) : T(1) / T(36));
+}
+
+// ---- records -------------------------------------------------------------
+template <typename T>
+struct alignas(4 * sizeof(T)) V4 {
+  T x, y, z, w;
+};
+template <typename T>
+struct alignas(2 * sizeof(T)) V2 {
+  T x, y;
+};
+
+// Per-run parameters in device memory (read through the scalar cache).
+struct RunDev {
+  int32_t nx, ny, nz, visc;   // visc: -1 Newtonian, 0 polymer in A, 1 in B
+  int64_t n;                  // nodes of this run
+  int64_t off;                // node offset of this run inside the pools
+  int32_t target;             // steps to take in the current step call
+  int32_t base;               // parity of the run's step count at call start
+  int32_t min_cc;             // smallest droplet piece counted (nodes)
+  int32_t pad0;
+  double u_wall, G;
+  double tau[2], inv_tau[2];
+  double inv_tauP, etaP_over_tauP, L2;
+  double chi_lo, inv_chi_range;
+  double rho0[2];             // FP16S shift densities
+};
+
+// One tile of the step launch: a bx*by column block at (x0, y0) covering
+// z0 .. z0+bz-1 of run `run` (run < 0: padding entry, skipped).
+struct Tile {
+  int32_t run, x0, y0, z0;
+};
+
+// ---- storage conversions -------------------------------------------------
+// Populations are stored as S and converted to the arithmetic type T; the
+// FP16 format stores the shifted value f - w_i rho0 (round to nearest even).
+template <typename T, typename S>
+struct Store;
+
+template <typename T>
+struct Store<T, T> {
+  static __device__ __forceinline__ T load(const T* p, int64_t k, T /*shift*/) { return p[k]; }
+  static __device__ __forceinline__ void store(T* p, int64_t k, T v, T /*shift*/) { p[k] = v; }
+  static __device__ __forceinline__ T roundtrip(T v, T /*shift*/) { return v; }
+};
+
+template <>
+struct Store<float, __half> {
+  static __device__ __forceinline__ float load(const __half* p, int64_t k, float shift) {
+    return __half2float(p[k]) + shift;
+  }
+  static __device__ __forceinline__ void store(__half* p, int64_t k, float v, float shift) {
+    p[k] = __float2half_rn(v - shift);
+  }
+  static __device__ __forceinline__ float roundtrip(float v, float shift) {
+    return __half2float(__float2half_rn(v - shift)) + shift;
+  }
+};
+
+// ---- pools: all runs' fields, concatenated per field -----------------------
+template <typename T, typename S>
+struct Pools {
+  S* f[2];            // [38][n] per run (component-major, then direction)
+  V2<T>* rho[2];      // (rho_A, rho_B) per node
+  T* j[2];            // [6][n] per run: j_A xyz, j_B xyz
+  T* C[2];            // [6][n] per run: xx yy zz xy xz yz
+  V4<T>* recA;        // (rho_A, u^eq_A) per node, written by the force pass
+  V4<T>* recB;        // (rho_B, u^eq_B)
+  T* u;               // [3][n] per run: physical velocity
+  uint32_t* status;   // per run: bit 0 non-finite, bit 1 tr C >= L^2
+};
+
+constexpr uint32_t ST_NAN = 1u;
+constexpr uint32_t ST_FENE = 2u;
+constexpr uint32_t ST_CC = 4u;   // component labelling hit its iteration cap
+
+__device__ __forceinline__ int wrapm(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+__device__ __forceinline__ int clampz(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
+
+}  // namespace lbm

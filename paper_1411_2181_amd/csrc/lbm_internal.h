@@ -1,0 +1,63 @@
+// Internal interface between the host library and the kernel translation
+// units (not part of the public C ABI).
+#pragma once
+
+#include "lbm_device.h"
+
+namespace lbm {
+
+template <typename T, typename S>
+struct StepArgs {
+  Pools<T, S> P;
+  const RunDev* runs;
+  const Tile* tiles;
+  int32_t ntiles;
+  int32_t bz;
+  const int32_t* gstep;   // step index within the current step call
+};
+
+// Number of per-block partial values of the observable reduction.
+constexpr int NOBS = 16;
+enum ObsSlot {
+  OB_MA = 0, OB_MB, OB_W, OB_WX, OB_WY, OB_WZ, OB_WXX, OB_WXZ, OB_WZZ,
+  OB_U2MAX, OB_TRCMAX, OB_XMIN, OB_XMAX, OB_NONFINITE, OB_PAD0, OB_PAD1
+};
+// blocks per run of the per-node auxiliary kernels (init, moments, observe,
+// component labelling)
+constexpr int AUX_BLOCKS = 128;
+constexpr int AUX_THREADS = 256;
+
+template <typename T, typename S>
+struct AuxArgs {
+  Pools<T, S> P;
+  const RunDev* runs;
+  int32_t nruns;
+  int32_t use_parity;      // parity of each run = (runs[r].base) & 1 when 1, else 0
+  double* partials;        // [nruns][AUX_BLOCKS][NOBS]
+  double* obs;             // [nruns][NOBS]
+  int32_t* labels;         // per node (component labelling)
+  int32_t* counts;         // per node
+  int32_t* ncomp;          // per run
+  const double* radius_centre;  // [nruns][4]: R, cx, cy, cz  (init only)
+  const double* rho_init;       // [nruns][2]: rho_major, rho_minor (init only)
+};
+
+template <typename T, typename S>
+void launch_force(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s);
+template <typename T, typename S>
+void launch_update(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s);
+
+template <typename T, typename S>
+void launch_init(const AuxArgs<T, S>& a, hipStream_t s);
+template <typename T, typename S>
+void launch_moments(const AuxArgs<T, S>& a, hipStream_t s);
+template <typename T, typename S>
+void launch_observe(const AuxArgs<T, S>& a, hipStream_t s);
+template <typename T, typename S>
+void launch_components(const AuxArgs<T, S>& a, hipStream_t s);
+
+void launch_set_step(int32_t* gstep, int32_t v, hipStream_t s);
+void launch_inc_step(int32_t* gstep, hipStream_t s);
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+
+}  // namespace lbm

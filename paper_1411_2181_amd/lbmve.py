@@ -1,0 +1,277 @@
+"""ctypes binding of liblbmve.so (the C ABI of include/lbmve.h).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels
+of the library.  PyTorch provides the device workspace (a uint8 tensor) and
+the stream (torch's current stream).  If the library has not been built the
+import of this module succeeds but every constructor raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbmve.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSUP, LBM_ENAN, LBM_EFENE = 0, -1, -2, -3, -4, -5, -6
+PRECISION = {"fp64": 0, "fp32": 1, "fp16s": 2}
+FIELD = {"f": 0, "C": 1, "rho": 2, "u": 3}
+FIELD_COMPONENTS = {"f": 38, "C": 6, "rho": 2, "u": 3}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+
+
+class LbmParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("u_wall", ctypes.c_double),
+        ("radius", ctypes.c_double),
+        ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("cz", ctypes.c_double),
+        ("rho_major", ctypes.c_double), ("rho_minor", ctypes.c_double),
+        ("G", ctypes.c_double),
+        ("tau", ctypes.c_double * 2),
+        ("tau_P", ctypes.c_double * 2),
+        ("eta_P", ctypes.c_double * 2),
+        ("L2", ctypes.c_double * 2),
+        ("chi_lo", ctypes.c_double), ("chi_hi", ctypes.c_double),
+        ("rho0", ctypes.c_double * 2),
+    ]
+
+
+class LbmObs(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64),
+        ("mass", ctypes.c_double * 2),
+        ("weight", ctypes.c_double),
+        ("centroid", ctypes.c_double * 3),
+        ("inertia", ctypes.c_double * 3),
+        ("D", ctypes.c_double),
+        ("theta_deg", ctypes.c_double),
+        ("Lp", ctypes.c_double),
+        ("umax", ctypes.c_double),
+        ("trC_max", ctypes.c_double),
+        ("n_components", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return dict(step=int(self.step), mass=(self.mass[0], self.mass[1]),
+                    weight=self.weight, centroid=tuple(self.centroid),
+                    inertia=tuple(self.inertia), D=self.D,
+                    theta_deg=self.theta_deg, Lp=self.Lp, umax=self.umax,
+                    trC_max=self.trC_max, n_components=int(self.n_components),
+                    status=int(self.status))
+
+
+class LbmLaunch(ctypes.Structure):
+    _fields_ = [("bx", ctypes.c_int32), ("by", ctypes.c_int32), ("bz", ctypes.c_int32),
+                ("persistent", ctypes.c_int32)]
+
+
+_lib = None
+
+_SIGNATURES = {
+    "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "lbm_validate": (ctypes.c_int, [ctypes.POINTER(LbmParams)]),
+    "lbm_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(LbmParams), ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm_init": (ctypes.c_int, [ctypes.POINTER(LbmParams), ctypes.c_void_p, ctypes.c_size_t,
+                                ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "lbm_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "lbm_observe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(LbmObs)]),
+    "lbm_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t]),
+    "lbm_import": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t]),
+    "lbm_destroy": (None, [ctypes.c_void_p]),
+    "lbm_get_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(LbmLaunch)]),
+    "lbm_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(LbmLaunch)]),
+    "lbm_step_profiled": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "lbm_steps_done": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "lbm_batch_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(LbmParams), ctypes.c_int32,
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm_batch_init": (ctypes.c_int, [ctypes.POINTER(LbmParams), ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "lbm_batch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "lbm_batch_observe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(LbmObs)]),
+    "lbm_batch_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_size_t]),
+    "lbm_batch_import": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_size_t]),
+    "lbm_batch_nruns": (ctypes.c_int32, [ctypes.c_void_p]),
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1411_2181_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().lbm_strerror(code).decode()
+    except RuntimeError:
+        return "library not loaded"
+
+
+def _check(code: int, what: str):
+    if code != LBM_OK:
+        raise LbmError(code, what)
+
+
+def make_params(d: dict, precision: str = "fp64") -> LbmParams:
+    """Pack a parameter dictionary (names of lbm_params) into the C struct."""
+    p = LbmParams()
+    p.nx, p.ny, p.nz = int(d["nx"]), int(d["ny"]), int(d["nz"])
+    p.precision = PRECISION[precision]
+    p.u_wall = float(d["u_wall"])
+    p.radius = float(d["radius"])
+    p.cx, p.cy, p.cz = float(d.get("cx", -1.0)), float(d.get("cy", -1.0)), float(d.get("cz", -1.0))
+    p.rho_major, p.rho_minor = float(d["rho_major"]), float(d["rho_minor"])
+    p.G = float(d["G"])
+    for name in ("tau", "tau_P", "eta_P", "L2"):
+        v = d[name]
+        arr = getattr(p, name)
+        arr[0], arr[1] = float(v[0]), float(v[1])
+    p.chi_lo = float(d.get("chi_lo", 0.0))
+    p.chi_hi = float(d.get("chi_hi", 0.0))
+    r0 = d.get("rho0", (0.0, 0.0))
+    p.rho0[0], p.rho0[1] = float(r0[0]), float(r0[1])
+    return p
+
+
+def validate(d: dict, precision: str = "fp64") -> int:
+    p = make_params(d, precision)
+    return lib().lbm_validate(ctypes.byref(p))
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Batch:
+    """Independent runs of one precision advanced together (one run = a
+    batch of one).  Holds its device workspace as a torch uint8 tensor."""
+
+    def __init__(self, runs: Sequence[dict], precision: str = "fp64", device="cuda:0",
+                 stream=None):
+        import torch
+        L = lib()
+        self.nruns = len(runs)
+        self.dicts = [dict(r) for r in runs]
+        self.precision = precision
+        arr = (LbmParams * self.nruns)(*[make_params(r, precision) for r in runs])
+        self._arr = arr
+        nbytes = ctypes.c_size_t()
+        _check(L.lbm_batch_workspace_bytes(arr, self.nruns, ctypes.byref(nbytes)), "workspace size")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.lbm_batch_init(arr, self.nruns, ctypes.c_void_p(self.workspace.data_ptr()),
+                                    nbytes.value, ctypes.c_void_p(_stream_ptr(self.stream)),
+                                    ctypes.byref(ctx)), "init")
+        self._ctx = ctx
+
+    # ------------------------------------------------------------------
+    def _c(self):
+        if self._ctx is None or not self._ctx.value:
+            raise RuntimeError("context destroyed")
+        return self._ctx
+
+    def step(self, steps):
+        """Advance every run by ``steps`` (int) or run r by steps[r]."""
+        if np.isscalar(steps):
+            steps = [int(steps)] * self.nruns
+        a = (ctypes.c_int32 * self.nruns)(*[int(s) for s in steps])
+        _check(lib().lbm_batch_step(self._c(), a), "step")
+
+    def observe(self, components: bool = False, check: bool = False) -> list:
+        out = (LbmObs * self.nruns)()
+        code = lib().lbm_batch_observe(self._c(), int(components), out)
+        if code in (LBM_EINVAL, LBM_EHIP) or (check and code != LBM_OK):
+            raise LbmError(code, "observe")
+        return [o.as_dict() for o in out]
+
+    def export(self, field: str, run: int = 0) -> np.ndarray:
+        d = self.dicts[run]
+        shape = (d["nz"], d["ny"], d["nx"])
+        n = FIELD_COMPONENTS[field] * int(np.prod(shape))
+        buf = np.empty(n, dtype=np.float64)
+        _check(lib().lbm_batch_export(self._c(), run, FIELD[field], buf.ctypes.data, n), f"export {field}")
+        if field == "f":
+            return buf.reshape((2, 19) + shape)
+        return buf.reshape((FIELD_COMPONENTS[field],) + shape)
+
+    def import_(self, field: str, values: np.ndarray, run: int = 0):
+        v = np.ascontiguousarray(values, dtype=np.float64).ravel()
+        _check(lib().lbm_batch_import(self._c(), run, FIELD[field], v.ctypes.data, v.size), f"import {field}")
+
+    def step_profiled(self, nsteps: int):
+        """Eager steps with HIP events around each pass; returns the summed
+        (force pass, collide-stream pass) durations in milliseconds."""
+        ms = (ctypes.c_double * 2)()
+        _check(lib().lbm_step_profiled(self._c(), int(nsteps), ms), "step_profiled")
+        return float(ms[0]), float(ms[1])
+
+    def steps_done(self, run: int = 0) -> int:
+        v = ctypes.c_int64()
+        _check(lib().lbm_steps_done(self._c(), run, ctypes.byref(v)), "steps_done")
+        return int(v.value)
+
+    @property
+    def launch(self) -> dict:
+        l = LbmLaunch()
+        _check(lib().lbm_get_launch(self._c(), ctypes.byref(l)), "get_launch")
+        return dict(bx=l.bx, by=l.by, bz=l.bz, persistent=l.persistent)
+
+    def set_launch(self, bx=64, by=4, bz=1, persistent=0):
+        l = LbmLaunch(bx, by, bz, persistent)
+        _check(lib().lbm_set_launch(self._c(), ctypes.byref(l)), "set_launch")
+
+    def close(self):
+        if self._ctx is not None and self._ctx.value:
+            lib().lbm_destroy(self._ctx)
+        self._ctx = None
+        self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Solver(Batch):
+    """A single run."""
+
+    def __init__(self, params: dict, precision: str = "fp64", device="cuda:0", stream=None):
+        super().__init__([params], precision, device, stream)
+
+    def observe(self, components: bool = False, check: bool = False) -> dict:
+        return super().observe(components, check)[0]

@@ -1,0 +1,253 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bar (FP64): per exported field max|GPU - oracle| / max|oracle| <= 1e-10 after
+2000 steps of the 32^3 droplet cases, and <= 1e-12 after 10 steps from random
+states on ragged lattices; observables relative <= 1e-10 (orientation
+absolute <= 1e-8 degrees).  Integer results (component counts) bit-exact.
+Bit-identity where the arithmetic is the same: launch shapes, batches,
+repeated runs and checkpoint/restart.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as WL
+from oracle import d3q19
+from oracle.components import component_sizes
+from oracle.observables import observe
+from oracle.solver import Oracle
+from tests import oracle_pool
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1411_2181_amd import lbmve
+    lbmve.lib()
+    return lbmve
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _fields(s):
+    return dict(f=s.export("f"), C=s.export("C"), rho=s.export("rho"), u=s.export("u"))
+
+
+def _check_obs(g, o, tol=1e-10):
+    assert abs(g["mass"][0] - o["mass"][0]) <= tol * abs(o["mass"][0])
+    assert abs(g["mass"][1] - o["mass"][1]) <= tol * abs(o["mass"][1])
+    assert abs(g["D"] - o["D"]) <= tol * max(abs(o["D"]), 1e-6)
+    assert abs(g["theta_deg"] - o["theta_deg"]) <= 1e-8 or abs(o["D"]) < 1e-6
+    for a in range(3):
+        assert abs(g["centroid"][a] - o["centroid"][a]) <= tol * 100
+    assert g["Lp"] == o["Lp"]
+    assert abs(g["trC_max"] - o["trC_max"]) <= tol * o["trC_max"]
+    if "umax" in o:
+        assert abs(g["umax"] - o["umax"]) <= tol * max(o["umax"], 1e-12)
+
+
+def test_init_state_exact(lbm):
+    d = WL.small_droplet_viscoelastic()
+    s = lbm.Solver(d, "fp64")
+    o = Oracle(d)
+    assert np.array_equal(s.export("f"), o.f)
+    assert np.array_equal(s.export("C"), o.C)
+    s.close()
+
+
+@pytest.mark.parametrize("shape_xyz", [(17, 9, 12), (33, 5, 40)])
+@pytest.mark.parametrize("visc", ["none", "A", "B"])
+def test_random_state_ragged_parity(lbm, shape_xyz, visc):
+    nx, ny, nz = shape_xyz
+    eta = {"none": (0.0, 0.0), "A": (0.05, 0.0), "B": (0.0, 0.05)}[visc]
+    d = WL.base_params(nx=nx, ny=ny, nz=nz, radius=3.0, u_wall=0.02, tau=(0.8, 1.3),
+                       tau_P=(20.0, 30.0), eta_P=eta, L2=(60.0, 80.0))
+    print(f"case ragged {shape_xyz} visc={visc}", flush=True)
+    f0 = WL.random_populations((nz, ny, nx), d3q19.W, seed=7)
+    C0 = WL.random_conformation((nz, ny, nx), seed=8)
+    s = lbm.Solver(d, "fp64")
+    s.import_("f", f0)
+    s.import_("C", C0)
+    s.step(10)
+    g = _fields(s)
+    o = Oracle(d, f=f0, C=C0)
+    o.step(10)
+    assert rel(g["f"], o.f) <= 1e-12
+    assert rel(g["C"], o.C) <= 1e-12
+    assert rel(g["rho"], o.density()) <= 1e-12
+    assert rel(g["u"], o.velocity()) <= 1e-11
+    go = s.observe()
+    oo = observe(o.f, o.C, o.velocity())
+    assert abs(go["mass"][0] - oo["mass"][0]) <= 1e-12 * oo["mass"][0]
+    assert abs(go["trC_max"] - oo["trC_max"]) <= 1e-12 * oo["trC_max"]
+    s.close()
+
+
+CASES = {"newtonian": WL.small_newtonian, "droplet_visc": WL.small_droplet_viscoelastic,
+         "matrix_visc": WL.small_matrix_viscoelastic}
+
+
+@pytest.fixture(scope="module")
+def oracle_2000():
+    # start the three long oracle runs in worker processes right away
+    return {k: oracle_pool.submit(fn(), 2000) for k, fn in CASES.items()}
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("case", list(CASES))
+def test_small_droplet_2000_steps_parity(lbm, oracle_2000, case):
+    d = CASES[case]()
+    print(f"case 32^3 {case} 2000 steps", flush=True)
+    s = lbm.Solver(d, "fp64")
+    s.step(2000)
+    g = _fields(s)
+    go = s.observe(components=True)
+    o = oracle_2000[case].result()
+    for k in ("f", "C", "rho", "u"):
+        assert rel(g[k], o[k]) <= 1e-10, k
+    _check_obs(go, o["obs"])
+    assert go["status"] == 0 and o["status"] == 0
+    assert go["n_components"] == 1
+    # the droplet did deform under shear (the check is not trivial)
+    assert go["D"] > 1e-3
+    s.close()
+
+
+def test_launch_shapes_bit_identical(lbm):
+    d = WL.small_droplet_viscoelastic()
+    ref = None
+    for shape in [dict(bx=64, by=4, bz=1), dict(bx=32, by=2, bz=3),
+                  dict(bx=128, by=1, bz=8, persistent=64), dict(bx=256, by=1, bz=2)]:
+        s = lbm.Solver(d, "fp64")
+        s.set_launch(**shape)
+        s.step(25)
+        out = (s.export("f"), s.export("C"))
+        s.close()
+        if ref is None:
+            ref = out
+        else:
+            assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), shape
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16s"])
+def test_repeat_and_checkpoint_bit_identical(lbm, precision):
+    d = WL.small_matrix_viscoelastic()
+    a = lbm.Solver(d, precision)
+    a.step(60)
+    fa, Ca = a.export("f"), a.export("C")
+    b = lbm.Solver(d, precision)
+    b.step(60)
+    assert np.array_equal(b.export("f"), fa) and np.array_equal(b.export("C"), Ca)
+    # checkpoint at step 30, restart in a fresh context
+    c = lbm.Solver(d, precision)
+    c.step(30)
+    fc, Cc = c.export("f"), c.export("C")
+    r = lbm.Solver(d, precision)
+    r.import_("f", fc)
+    r.import_("C", Cc)
+    r.step(30)
+    assert np.array_equal(r.export("f"), fa) and np.array_equal(r.export("C"), Ca)
+    for s in (a, b, c, r):
+        s.close()
+
+
+def test_batch_equals_single_runs(lbm):
+    runs = [WL.small_droplet_viscoelastic(),
+            WL.base_params(nx=20, ny=24, nz=18, radius=5.0, tau=(1.0, 0.8),
+                           tau_P=(1.0, 50.0), eta_P=(0.0, 0.05), u_wall=0.01),
+            WL.base_params(nx=17, ny=9, nz=12, radius=3.0, u_wall=0.02)]
+    steps = [30, 17, 25]
+    for prec in ("fp64", "fp32"):
+        b = lbm.Batch(runs, prec)
+        b.step(steps)
+        for r, d in enumerate(runs):
+            s = lbm.Solver(d, prec)
+            s.step(steps[r])
+            assert np.array_equal(b.export("f", r), s.export("f")), (prec, r)
+            assert np.array_equal(b.export("C", r), s.export("C")), (prec, r)
+            assert b.steps_done(r) == steps[r]
+            s.close()
+        obs = b.observe()
+        assert [o["step"] for o in obs] == steps
+        b.close()
+
+
+def test_nan_and_fene_flags(lbm):
+    d = WL.small_droplet_viscoelastic()
+    s = lbm.Solver(d, "fp64")
+    s.step(3)
+    assert s.observe()["status"] == 0
+    f = s.export("f")
+    f[0, 3, 10, 10, 10] = np.nan
+    s.import_("f", f)
+    s.step(2)
+    assert s.observe()["status"] == lbm.LBM_ENAN
+    s.close()
+    s = lbm.Solver(d, "fp64")
+    C = s.export("C")
+    C[0, 16, 16, 16] = 150.0          # tr C > L^2 = 100 inside the droplet
+    s.import_("C", C)
+    s.step(1)
+    assert s.observe()["status"] == lbm.LBM_EFENE
+    s.close()
+
+
+def test_batch_flags_only_the_poisoned_run(lbm):
+    runs = [WL.small_newtonian(), WL.small_newtonian(), WL.small_newtonian()]
+    b = lbm.Batch(runs, "fp32")
+    f = b.export("f", 1)
+    f[1, 5, 3, 3, 3] = np.inf
+    b.import_("f", f, run=1)
+    b.step(5)
+    st = [o["status"] for o in b.observe()]
+    assert st == [0, lbm.LBM_ENAN, 0]
+    b.close()
+
+
+def test_component_count_matches_oracle(lbm):
+    # two droplets plus a tiny speck: count of pieces >= 1% of the initial
+    # droplet volume (R = 8 -> 2109 nodes -> 22 nodes)
+    d = WL.small_newtonian()
+    nz = ny = nx = 32
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    m = ((x - 8) ** 2 + (y - 16) ** 2 + (z - 16) ** 2 < 25) \
+        | ((x - 24) ** 2 + (y - 16) ** 2 + (z - 16) ** 2 < 30) \
+        | ((x == 0) & (y == 0) & (z == 3))
+    # a droplet split across the periodic x seam is one piece
+    m |= ((np.minimum(x, 32 - x) ** 2 + (y - 5) ** 2 + (z - 5) ** 2) < 9)
+    rA = np.where(m, 1.0, 0.04)
+    rB = np.where(m, 0.04, 1.0)
+    f = np.stack([d3q19.W[:, None, None, None] * rA, d3q19.W[:, None, None, None] * rB])
+    s = lbm.Solver(d, "fp64")
+    s.import_("f", f)
+    got = s.observe(components=True)["n_components"]
+    sizes = component_sizes(m)
+    want = sum(1 for v in sizes if v >= 22)
+    assert got == want == 3
+    s.close()
+
+
+@pytest.mark.parametrize("precision,d_tol,u_tol", [("fp32", 1e-3, 1e-4), ("fp16s", 5e-3, None)])
+def test_reduced_precision_against_fp64(lbm, precision, d_tol, u_tol):
+    d = WL.small_droplet_viscoelastic()
+    ref = lbm.Solver(d, "fp64")
+    low = lbm.Solver(d, precision)
+    for _ in range(5):
+        ref.step(200)
+        low.step(200)
+    o64, olo = ref.observe(), low.observe()
+    assert abs(olo["D"] - o64["D"]) <= d_tol
+    u64, ulo = ref.export("u"), low.export("u")
+    err = math.sqrt(((ulo - u64) ** 2).sum() / (u64 ** 2).sum())
+    print(f"{precision}: D {olo['D']:.6e} vs {o64['D']:.6e}; u rel L2 {err:.3e}")
+    if u_tol is not None:
+        assert err <= u_tol
+    ref.close()
+    low.close()
