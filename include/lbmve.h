@@ -124,11 +124,12 @@ typedef struct {
 } lbm_obs;
 
 /* Launch shape of the step kernels (chosen by the autotuner).  A tile is
- * bx * by threads, each advancing bz nodes along z; persistent > 0 caps the
- * grid at that many workgroups, which then loop over the tile table. */
+ * bx * by columns of nodes advanced by one workgroup of bx * by threads,
+ * which marches up bz planes in z; persistent > 0 caps the grid at that many
+ * workgroups, which then loop over the tile table. */
 typedef struct {
-  int32_t bx, by, bz;    /* bx in {32,64,128,256}, by in {1,2,4,8},
-                            bx*by <= 256, 1 <= bz <= 16                      */
+  int32_t bx, by;        /* (64,4) (32,8) (128,2) (64,2) or (32,4)           */
+  int32_t bz;            /* planes per tile, 1 <= bz <= 1024                 */
   int32_t persistent;    /* 0 = one workgroup per tile                        */
 } lbm_launch;
 
@@ -163,8 +164,8 @@ void lbm_destroy(lbm_ctx* ctx);
 int lbm_get_launch(const lbm_ctx* ctx, lbm_launch* out);
 int lbm_set_launch(lbm_ctx* ctx, const lbm_launch* in);
 /* Advance every run by nsteps with eager launches and HIP events around
- * each pass; ms_pass[0] / ms_pass[1] receive the summed durations of the
- * force pass and of the collide-stream-FENE-P pass (for roofline accounting).
+ * each pass; ms_pass[0..2] receive the summed durations of the force pass,
+ * the collide-stream pass and the FENE-P pass (for roofline accounting).
  * Synchronises. */
 int lbm_step_profiled(lbm_ctx* ctx, int32_t nsteps, double* ms_pass);
 /* Steps actually taken by run r since init. */

@@ -23,9 +23,10 @@ import numpy as np
 
 from . import lbmve, physics
 
-# (G, relaxation times) groups: the Shan-Chen coupling of the small
-# Newtonian case and the weaker coupling used for the mapped workloads
-GROUPS = ((0.9, (1.0, 1.5, 2.0)), (0.7, (1.0, 2.0, 3.0, 4.0, 5.0)))
+# (G, relaxation times) groups; with the velocity-shift forcing the droplet
+# is Laplace-consistent only for tau of about 1..1.5 at G = 0.9 (beyond that
+# the minority densities drift with tau and droplets dissolve or distort)
+GROUPS = ((0.9, (1.0, 1.25, 1.5, 1.75)),)
 RADII = (10.0, 12.0, 14.0)
 BOX = 48
 STEPS = 4000
@@ -77,7 +78,7 @@ def calibrate(groups=GROUPS, radii=RADII, steps=STEPS, precision="fp32"):
         sigma = float((dp * x).sum() / (x * x).sum()) if ok else float("nan")
         spread = float((dp / x).max() / (dp / x).min() - 1.0) if ok else float("nan")
         # a usable entry: finite, Laplace-consistent across the radii (5 %)
-        ok = ok and spread < 0.05 and sigma > 0.0
+        ok = ok and 0.0 <= spread < 0.05 and sigma > 0.0
         entries.append(dict(G=G, tau_A=ta, tau_B=tb, sigma=sigma, laplace_spread=spread,
                             usable=ok, radii=[float(v[1]) for v in vals],
                             spurious_umax=max(float(v[2]) for v in vals)))

@@ -63,20 +63,25 @@ struct Layout {
   int64_t tiles_cap;
 };
 
+// Stride between the component arrays of one run's field: the node count
+// rounded up to 64 and offset by 96 more, so that arrays of a power-of-two
+// lattice do not start at the same HBM channel.
+int64_t ld_of(int64_t n) { return (n + 63) / 64 * 64 + 96; }
+
 size_t elem_S(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2); }
 size_t elem_T(int prec) { return prec == LBM_FP64 ? 8 : 4; }
 
 int64_t max_tiles(const lbm_params* p, int32_t nruns) {
-  // smallest tile: bx = 32, by = 1, bz = 1
+  // smallest tile: bx = 32, by = 4, bz = 1
   int64_t t = 0;
-  for (int r = 0; r < nruns; ++r) t += (int64_t)((p[r].nx + 31) / 32) * p[r].ny * p[r].nz;
+  for (int r = 0; r < nruns; ++r) t += (int64_t)((p[r].nx + 31) / 32) * ((p[r].ny + 3) / 4) * p[r].nz;
   return (t + 7) / 8 * 8;
 }
 
 Layout make_layout(const lbm_params* p, int32_t nruns) {
   Layout L{};
-  int64_t nodes = 0;
-  for (int r = 0; r < nruns; ++r) nodes += (int64_t)p[r].nx * p[r].ny * p[r].nz;
+  int64_t nodes = 0;   // padded: sum of the runs' array strides
+  for (int r = 0; r < nruns; ++r) nodes += ld_of((int64_t)p[r].nx * p[r].ny * p[r].nz);
   const int prec = p[0].precision;
   const size_t s = elem_S(prec), t = elem_T(prec);
   size_t off = 0;
@@ -115,7 +120,7 @@ struct lbm_ctx {
   std::vector<int64_t> done;
   char* ws = nullptr;
   Layout L{};
-  lbm_launch launch{64, 4, 1, 0};
+  lbm_launch launch{64, 4, 16, 0};
   int64_t ntiles = 0;          // entries of the (XCD-permuted) tile table
   std::map<int, hipGraphExec_t> graphs;
   std::map<int, hipGraph_t> graph_src;
@@ -131,7 +136,7 @@ lbm::Pools<T, S> pools(const lbm_ctx* c) {
   lbm::Pools<T, S> P;
   for (int b = 0; b < 2; ++b) {
     P.f[b] = c->at<S>(c->L.f[b]);
-    P.rho[b] = c->at<lbm::V2<T>>(c->L.rho[b]);
+    P.rho[b] = c->at<T>(c->L.rho[b]);
     P.j[b] = c->at<T>(c->L.j[b]);
     P.C[b] = c->at<T>(c->L.C[b]);
   }
@@ -151,6 +156,8 @@ lbm::StepArgs<T, S> step_args(const lbm_ctx* c) {
   a.ntiles = (int32_t)c->ntiles;
   a.bz = c->launch.bz;
   a.gstep = c->at<int32_t>(c->L.gstep);
+  a.any_visc = 0;
+  for (const RunDev& R : c->runs) a.any_visc |= R.visc >= 0;
   return a;
 }
 
@@ -231,6 +238,7 @@ RunDev make_run(const lbm_params& p, int64_t off) {
   R.nx = p.nx; R.ny = p.ny; R.nz = p.nz;
   R.visc = p.eta_P[0] > 0.0 ? 0 : (p.eta_P[1] > 0.0 ? 1 : -1);
   R.n = (int64_t)p.nx * p.ny * p.nz;
+  R.ld = ld_of(R.n);
   R.off = off;
   R.target = 0;
   R.base = 0;
@@ -339,7 +347,8 @@ void enqueue_step(lbm_ctx* c, hipStream_t s) {
     using S = std::remove_pointer_t<decltype(ss)>;
     const auto a = step_args<T, S>(c);
     lbm::launch_force<T, S>(a, grid, block, s);
-    lbm::launch_update<T, S>(a, grid, block, s);
+    lbm::launch_collide<T, S>(a, grid, block, s);
+    lbm::launch_fene<T, S>(a, grid, block, s);
   });
   lbm::launch_inc_step(c->at<int32_t>(c->L.gstep), s);
 }
@@ -482,7 +491,7 @@ int lbm_batch_init(const lbm_params* runs, int32_t nruns, void* ws, size_t bytes
   std::vector<double> rc(4 * nruns), rinit(2 * nruns);
   for (int r = 0; r < nruns; ++r) {
     c->runs.push_back(make_run(runs[r], off));
-    off += c->runs.back().n;
+    off += c->runs.back().ld;
     const lbm_params& p = runs[r];
     const bool centre = p.cx < 0;
     rc[4 * r] = p.radius;
@@ -536,10 +545,11 @@ int lbm_get_launch(const lbm_ctx* c, lbm_launch* out) {
 int lbm_set_launch(lbm_ctx* c, const lbm_launch* in) {
   if (!c || !in) return LBM_EINVAL;
   const lbm_launch l = *in;
-  const bool bx_ok = l.bx == 32 || l.bx == 64 || l.bx == 128 || l.bx == 256;
-  const bool by_ok = l.by == 1 || l.by == 2 || l.by == 4 || l.by == 8;
-  if (!bx_ok || !by_ok || l.bx * l.by > 256 || l.bz < 1 || l.bz > 16 || l.persistent < 0)
-    return LBM_EINVAL;
+  // block shapes with a compiled update-pass instance
+  const bool shape_ok = (l.bx == 64 && l.by == 4) || (l.bx == 32 && l.by == 8) ||
+                        (l.bx == 128 && l.by == 2) || (l.bx == 64 && l.by == 2) ||
+                        (l.bx == 32 && l.by == 4);
+  if (!shape_ok || l.bz < 1 || l.bz > 1024 || l.persistent < 0) return LBM_EINVAL;
   const lbm_launch old = c->launch;
   c->launch = l;
   const int e = build_tiles(c);
@@ -560,12 +570,12 @@ int lbm_batch_step(lbm_ctx* c, const int32_t* steps) {
 
 int lbm_step_profiled(lbm_ctx* c, int32_t nsteps, double* ms_pass) {
   if (!c || nsteps < 0 || !ms_pass) return LBM_EINVAL;
-  ms_pass[0] = ms_pass[1] = 0.0;
+  ms_pass[0] = ms_pass[1] = ms_pass[2] = 0.0;
   if (nsteps == 0) return LBM_OK;
   std::vector<int32_t> t(c->nruns, nsteps);
   int e = set_targets(c, t.data());
   if (e) return e;
-  std::vector<hipEvent_t> ev(3 * (size_t)nsteps, nullptr);
+  std::vector<hipEvent_t> ev(4 * (size_t)nsteps, nullptr);
   for (auto& x : ev)
     if (hipEventCreate(&x) != hipSuccess) { e = LBM_EHIP; break; }
   const dim3 grid = step_grid(c), block(c->launch.bx, c->launch.by);
@@ -574,21 +584,23 @@ int lbm_step_profiled(lbm_ctx* c, int32_t nsteps, double* ms_pass) {
       using T = std::remove_pointer_t<decltype(tt)>;
       using S = std::remove_pointer_t<decltype(ss)>;
       const auto a = step_args<T, S>(c);
-      hipEventRecord(ev[3 * k], c->stream);
+      hipEventRecord(ev[4 * k], c->stream);
       lbm::launch_force<T, S>(a, grid, block, c->stream);
-      hipEventRecord(ev[3 * k + 1], c->stream);
-      lbm::launch_update<T, S>(a, grid, block, c->stream);
-      hipEventRecord(ev[3 * k + 2], c->stream);
+      hipEventRecord(ev[4 * k + 1], c->stream);
+      lbm::launch_collide<T, S>(a, grid, block, c->stream);
+      hipEventRecord(ev[4 * k + 2], c->stream);
+      lbm::launch_fene<T, S>(a, grid, block, c->stream);
+      hipEventRecord(ev[4 * k + 3], c->stream);
     });
     lbm::launch_inc_step(c->at<int32_t>(c->L.gstep), c->stream);
   }
   if (!e && hipStreamSynchronize(c->stream) != hipSuccess) e = LBM_EHIP;
   for (int k = 0; k < nsteps && !e; ++k) {
-    float a = 0.f, b = 0.f;
-    if (hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]) != hipSuccess ||
-        hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]) != hipSuccess) { e = LBM_EHIP; break; }
-    ms_pass[0] += a;
-    ms_pass[1] += b;
+    for (int p = 0; p < 3; ++p) {
+      float v = 0.f;
+      if (hipEventElapsedTime(&v, ev[4 * k + p], ev[4 * k + p + 1]) != hipSuccess) { e = LBM_EHIP; break; }
+      ms_pass[p] += v;
+    }
   }
   for (auto& x : ev)
     if (x) hipEventDestroy(x);
@@ -668,10 +680,12 @@ int lbm_batch_export(lbm_ctx* c, int32_t run, int32_t field, double* host, size_
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   const size_t st = elem_S(c->prec), tt = elem_T(c->prec);
+  const int64_t LD = R.ld;
   std::vector<char> buf;
   if (field == LBM_FIELD_F) {
     buf.resize((size_t)want * st);
-    HIPCHK(hipMemcpy(buf.data(), c->ws + c->L.f[par] + (size_t)R.off * 38 * st, buf.size(), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy2D(buf.data(), N * st, c->ws + c->L.f[par] + (size_t)R.off * 38 * st, LD * st,
+                       N * st, 38, hipMemcpyDeviceToHost));
     for (int64_t k = 0; k < want; ++k) {
       if (c->prec == LBM_FP64) host[k] = ((double*)buf.data())[k];
       else if (c->prec == LBM_FP32) host[k] = ((float*)buf.data())[k];
@@ -684,21 +698,14 @@ int lbm_batch_export(lbm_ctx* c, int32_t run, int32_t field, double* host, size_
     return LBM_OK;
   }
   size_t src = 0;
-  if (field == LBM_FIELD_C) src = c->L.C[R.visc >= 0 ? par : 0] + (size_t)R.off * 6 * tt;
-  else if (field == LBM_FIELD_RHO) src = c->L.rho[par] + (size_t)R.off * 2 * tt;
-  else src = c->L.u + (size_t)R.off * 3 * tt;
+  int comps = 0;
+  if (field == LBM_FIELD_C) { src = c->L.C[R.visc >= 0 ? par : 0] + (size_t)R.off * 6 * tt; comps = 6; }
+  else if (field == LBM_FIELD_RHO) { src = c->L.rho[par] + (size_t)R.off * 2 * tt; comps = 2; }
+  else { src = c->L.u + (size_t)R.off * 3 * tt; comps = 3; }
   buf.resize((size_t)want * tt);
-  HIPCHK(hipMemcpy(buf.data(), c->ws + src, buf.size(), hipMemcpyDeviceToHost));
-  for (int64_t k = 0; k < want; ++k) {
-    const double v = tt == 8 ? ((double*)buf.data())[k] : (double)((float*)buf.data())[k];
-    if (field == LBM_FIELD_RHO) {
-      // device layout (rho_A, rho_B) per node -> [2][N]
-      const int64_t node = k / 2, comp = k % 2;
-      host[comp * N + node] = v;
-    } else {
-      host[k] = v;
-    }
-  }
+  HIPCHK(hipMemcpy2D(buf.data(), N * tt, c->ws + src, LD * tt, N * tt, comps, hipMemcpyDeviceToHost));
+  for (int64_t k = 0; k < want; ++k)
+    host[k] = tt == 8 ? ((double*)buf.data())[k] : (double)((float*)buf.data())[k];
   return LBM_OK;
 }
 
@@ -728,7 +735,8 @@ int lbm_batch_import(lbm_ctx* c, int32_t run, int32_t field, const double* host,
         ((__half*)buf.data())[k] = __float2half_rn((float)host[k] - shift);
       }
     }
-    HIPCHK(hipMemcpy(c->ws + c->L.f[par] + (size_t)R.off * 38 * st, buf.data(), buf.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy2D(c->ws + c->L.f[par] + (size_t)R.off * 38 * st, R.ld * st, buf.data(), N * st,
+                       N * st, 38, hipMemcpyHostToDevice));
   } else {
     buf.resize((size_t)want * tt);
     for (int64_t k = 0; k < want; ++k) {
@@ -737,7 +745,8 @@ int lbm_batch_import(lbm_ctx* c, int32_t run, int32_t field, const double* host,
     }
     // a Newtonian run never updates C, which stays at parity 0
     const int cp = R.visc >= 0 ? par : 0;
-    HIPCHK(hipMemcpy(c->ws + c->L.C[cp] + (size_t)R.off * 6 * tt, buf.data(), buf.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy2D(c->ws + c->L.C[cp] + (size_t)R.off * 6 * tt, R.ld * tt, buf.data(), N * tt,
+                       N * tt, 6, hipMemcpyHostToDevice));
   }
   // moments of every run at its current parity; clear this run's status
   std::vector<int32_t> zero(c->nruns, 0);

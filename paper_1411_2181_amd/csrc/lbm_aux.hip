@@ -23,9 +23,9 @@ template <typename T, typename S>
 __global__ void k_init(AuxArgs<T, S> a) {
   const int r = blockIdx.y;
   const RunDev& R = a.runs[r];
-  const int64_t N = R.n;
+  const int64_t N = R.ld;   // stride between the component arrays of a field
   int64_t beg, end;
-  node_range(N, beg, end);
+  node_range(R.n, beg, end);
   const double rad = a.radius_centre[4 * r], cx = a.radius_centre[4 * r + 1];
   const double cy = a.radius_centre[4 * r + 2], cz = a.radius_centre[4 * r + 3];
   const double rmaj = a.rho_init[2 * r], rmin = a.rho_init[2 * r + 1];
@@ -58,11 +58,11 @@ __global__ void k_moments(AuxArgs<T, S> a) {
   const int r = blockIdx.y;
   const RunDev& R = a.runs[r];
   const int par = a.use_parity ? (R.base & 1) : 0;
-  const int64_t N = R.n;
+  const int64_t N = R.ld;   // stride between the component arrays of a field
   int64_t beg, end;
-  node_range(N, beg, end);
+  node_range(R.n, beg, end);
   const S* f = a.P.f[par] + 38 * R.off;
-  V2<T>* rho = a.P.rho[par] + R.off;
+  T* rho = a.P.rho[par] + 2 * R.off;
   T* J = a.P.j[par] + 6 * R.off;
   for (int64_t n = beg + threadIdx.x; n < end; n += blockDim.x) {
     T rs[2], js[2][3];
@@ -80,8 +80,8 @@ __global__ void k_moments(AuxArgs<T, S> a) {
       }
       rs[s] = rsum; js[s][0] = jx; js[s][1] = jy; js[s][2] = jz;
     }
-    V2<T> ro; ro.x = rs[0]; ro.y = rs[1];
-    rho[n] = ro;
+    rho[n] = rs[0];
+    rho[N + n] = rs[1];
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -118,10 +118,10 @@ __global__ void __launch_bounds__(AUX_THREADS) k_obs_partial(AuxArgs<T, S> a) {
   const int r = blockIdx.y;
   const RunDev& R = a.runs[r];
   const int par = a.use_parity ? (R.base & 1) : 0;
-  const int64_t N = R.n;
+  const int64_t N = R.ld;   // stride between the component arrays of a field
   int64_t beg, end;
-  node_range(N, beg, end);
-  const V2<T>* rho = a.P.rho[par] + R.off;
+  node_range(R.n, beg, end);
+  const T* rho = a.P.rho[par] + 2 * R.off;
   // a Newtonian run never updates C, which stays at parity 0
   const T* C = a.P.C[R.visc >= 0 ? par : 0] + 6 * R.off;
   const T* U = a.P.u + 3 * R.off;
@@ -135,8 +135,7 @@ __global__ void __launch_bounds__(AUX_THREADS) k_obs_partial(AuxArgs<T, S> a) {
     const int x = (int)(n % R.nx);
     const int y = (int)((n / R.nx) % R.ny);
     const int z = (int)(n / ((int64_t)R.nx * R.ny));
-    const V2<T> rr = rho[n];
-    const double rA = (double)rr.x, rB = (double)rr.y;
+    const double rA = (double)rho[n], rB = (double)rho[N + n];
     const double phi = (rA - rB) / (rA + rB);
     const double w = phi > 0.0 ? phi : 0.0;
     const double xr = x - hx, yr = y - hy, zr = z - hz;
@@ -234,12 +233,11 @@ __global__ void k_cc_init(AuxArgs<T, S> a) {
   const int par = a.use_parity ? (R.base & 1) : 0;
   int64_t beg, end;
   node_range(R.n, beg, end);
-  const V2<T>* rho = a.P.rho[par] + R.off;
+  const T* rho = a.P.rho[par] + 2 * R.off;
   int32_t* L = a.labels + R.off;
   int32_t* cnt = a.counts + R.off;
   for (int64_t n = beg + threadIdx.x; n < end; n += blockDim.x) {
-    const V2<T> rr = rho[n];
-    L[n] = rr.x > rr.y ? (int32_t)n : -1;   // phi > 0  <=>  rho_A > rho_B
+    L[n] = rho[n] > rho[R.ld + n] ? (int32_t)n : -1;   // phi > 0  <=>  rho_A > rho_B
     cnt[n] = 0;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) a.ncomp[r] = 0;

@@ -37,7 +37,9 @@ struct alignas(2 * sizeof(T)) V2 {
 struct RunDev {
   int32_t nx, ny, nz, visc;   // visc: -1 Newtonian, 0 polymer in A, 1 in B
   int64_t n;                  // nodes of this run
-  int64_t off;                // node offset of this run inside the pools
+  int64_t ld;                 // stride between the component arrays of a field
+                              // (n padded so arrays do not alias in HBM channels)
+  int64_t off;                // offset of this run inside the pools, in strides
   int32_t target;             // steps to take in the current step call
   int32_t base;               // parity of the run's step count at call start
   int32_t min_cc;             // smallest droplet piece counted (nodes)
@@ -85,7 +87,7 @@ struct Store<float, __half> {
 template <typename T, typename S>
 struct Pools {
   S* f[2];            // [38][n] per run (component-major, then direction)
-  V2<T>* rho[2];      // (rho_A, rho_B) per node
+  T* rho[2];          // [2][n] per run: rho_A, rho_B
   T* j[2];            // [6][n] per run: j_A xyz, j_B xyz
   T* C[2];            // [6][n] per run: xx yy zz xy xz yz
   V4<T>* recA;        // (rho_A, u^eq_A) per node, written by the force pass

@@ -14,6 +14,7 @@ struct StepArgs {
   int32_t ntiles;
   int32_t bz;
   const int32_t* gstep;   // step index within the current step call
+  int32_t any_visc;       // some run of the batch carries a polymer phase
 };
 
 // Number of per-block partial values of the observable reduction.
@@ -45,7 +46,9 @@ struct AuxArgs {
 template <typename T, typename S>
 void launch_force(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s);
 template <typename T, typename S>
-void launch_update(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s);
+void launch_collide(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s);
+template <typename T, typename S>
+void launch_fene(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s);
 
 template <typename T, typename S>
 void launch_init(const AuxArgs<T, S>& a, hipStream_t s);

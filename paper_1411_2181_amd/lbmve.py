@@ -228,10 +228,10 @@ class Batch:
 
     def step_profiled(self, nsteps: int):
         """Eager steps with HIP events around each pass; returns the summed
-        (force pass, collide-stream pass) durations in milliseconds."""
-        ms = (ctypes.c_double * 2)()
+        (force, collide-stream, FENE-P) pass durations in milliseconds."""
+        ms = (ctypes.c_double * 3)()
         _check(lib().lbm_step_profiled(self._c(), int(nsteps), ms), "step_profiled")
-        return float(ms[0]), float(ms[1])
+        return float(ms[0]), float(ms[1]), float(ms[2])
 
     def steps_done(self, run: int = 0) -> int:
         v = ctypes.c_int64()

@@ -28,13 +28,13 @@ import os
 
 RHO_MAJOR = 1.0
 RHO_MINOR = 0.04
-# Shan-Chen coupling of the mapped workloads.  With the velocity-shift
-# forcing the minority density and the interface depend on tau; at G = 0.9 the
-# droplet is well behaved only for tau of about 1..2, which caps the viscosity
-# and hence the reachable Ca at low wall Mach number.  G = 0.7 stays stable up
-# to tau ~ 4-5, enough for Ca up to ~0.3-0.5 at U_w <= 0.1.
-G_DEFAULT = 0.7
-TAU_MAX = 5.0
+# Shan-Chen coupling of every workload.  With the velocity-shift forcing the
+# minority densities and the interface depend on tau; droplets stay
+# Laplace-consistent for tau of about 1..1.5 only (weaker couplings dissolve
+# the droplet at the larger tau a high matrix viscosity needs).  That window
+# caps the viscosity and hence the Ca reachable at a given wall speed.
+G_DEFAULT = 0.9
+TAU_MAX = 1.75
 CS2 = 1.0 / 3.0
 
 _HERE = os.path.dirname(os.path.abspath(__file__))

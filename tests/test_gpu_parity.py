@@ -123,8 +123,9 @@ def test_small_droplet_2000_steps_parity(lbm, oracle_2000, case):
 def test_launch_shapes_bit_identical(lbm):
     d = WL.small_droplet_viscoelastic()
     ref = None
-    for shape in [dict(bx=64, by=4, bz=1), dict(bx=32, by=2, bz=3),
-                  dict(bx=128, by=1, bz=8, persistent=64), dict(bx=256, by=1, bz=2)]:
+    for shape in [dict(bx=64, by=4, bz=1), dict(bx=32, by=8, bz=3),
+                  dict(bx=128, by=2, bz=8, persistent=64), dict(bx=64, by=2, bz=32),
+                  dict(bx=32, by=4, bz=5, persistent=8)]:
         s = lbm.Solver(d, "fp64")
         s.set_launch(**shape)
         s.step(25)
