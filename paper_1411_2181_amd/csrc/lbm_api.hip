@@ -114,7 +114,9 @@ Layout make_layout(const lbm_params* p, int32_t nruns) {
 struct lbm_ctx {
   int32_t nruns = 0, prec = 0;
   hipStream_t stream = nullptr;
-  hipStream_t cap = nullptr;
+  hipStream_t cap = nullptr;    // private streams used only to capture graphs
+  hipStream_t cap2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<lbm_params> prm;
   std::vector<RunDev> runs;
   std::vector<int64_t> done;
@@ -340,15 +342,27 @@ void enqueue_force(lbm_ctx* c, hipStream_t s) {
   });
 }
 
-void enqueue_step(lbm_ctx* c, hipStream_t s) {
+// One step.  With a side stream (graph capture) the FENE-P pass forks off
+// after the force pass and runs concurrently with the collide pass: both read
+// only state n and the force-pass outputs and write disjoint fields.
+void enqueue_step(lbm_ctx* c, hipStream_t s, hipStream_t side) {
   const dim3 grid = step_grid(c), block(c->launch.bx, c->launch.by);
   by_precision(c->prec, [&](auto* tt, auto* ss) {
     using T = std::remove_pointer_t<decltype(tt)>;
     using S = std::remove_pointer_t<decltype(ss)>;
     const auto a = step_args<T, S>(c);
     lbm::launch_force<T, S>(a, grid, block, s);
-    lbm::launch_collide<T, S>(a, grid, block, s);
-    lbm::launch_fene<T, S>(a, grid, block, s);
+    if (side && a.any_visc) {
+      hipEventRecord(c->ev_fork, s);
+      hipStreamWaitEvent(side, c->ev_fork, 0);
+      lbm::launch_fene<T, S>(a, grid, block, side);
+      lbm::launch_collide<T, S>(a, grid, block, s);
+      hipEventRecord(c->ev_join, side);
+      hipStreamWaitEvent(s, c->ev_join, 0);
+    } else {
+      lbm::launch_collide<T, S>(a, grid, block, s);
+      lbm::launch_fene<T, S>(a, grid, block, s);
+    }
   });
   lbm::launch_inc_step(c->at<int32_t>(c->L.gstep), s);
 }
@@ -357,9 +371,12 @@ int get_graph(lbm_ctx* c, int chunk, hipGraphExec_t* out) {
   auto it = c->graphs.find(chunk);
   if (it != c->graphs.end()) { *out = it->second; return LBM_OK; }
   if (!c->cap) HIPCHK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  if (!c->cap2) HIPCHK(hipStreamCreateWithFlags(&c->cap2, hipStreamNonBlocking));
+  if (!c->ev_fork) HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  if (!c->ev_join) HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-  for (int k = 0; k < chunk; ++k) enqueue_step(c, c->cap);
+  for (int k = 0; k < chunk; ++k) enqueue_step(c, c->cap, c->cap2);
   const hipError_t e = hipStreamEndCapture(c->cap, &g);
   if (e != hipSuccess || !g) return LBM_EHIP;
   hipGraphExec_t ex = nullptr;
@@ -531,6 +548,9 @@ void lbm_destroy(lbm_ctx* c) {
   if (c->stream || c->cap) hipStreamSynchronize(c->stream);
   destroy_graphs(c);
   if (c->cap) hipStreamDestroy(c->cap);
+  if (c->cap2) hipStreamDestroy(c->cap2);
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_join) hipEventDestroy(c->ev_join);
   delete c;
 }
 

@@ -63,10 +63,22 @@ struct Tile {
 template <typename T, typename S>
 struct Store;
 
+// Population stores stream past the caches (each value is read back only by
+// the next step, long after the line would have been evicted).
+#ifndef LBM_NT_STORES
+#define LBM_NT_STORES 1
+#endif
+
 template <typename T>
 struct Store<T, T> {
   static __device__ __forceinline__ T load(const T* p, int64_t k, T /*shift*/) { return p[k]; }
-  static __device__ __forceinline__ void store(T* p, int64_t k, T v, T /*shift*/) { p[k] = v; }
+  static __device__ __forceinline__ void store(T* p, int64_t k, T v, T /*shift*/) {
+#if LBM_NT_STORES
+    __builtin_nontemporal_store(v, p + k);
+#else
+    p[k] = v;
+#endif
+  }
   static __device__ __forceinline__ T roundtrip(T v, T /*shift*/) { return v; }
 };
 
@@ -76,7 +88,13 @@ struct Store<float, __half> {
     return __half2float(p[k]) + shift;
   }
   static __device__ __forceinline__ void store(__half* p, int64_t k, float v, float shift) {
+#if LBM_NT_STORES
+    const __half h = __float2half_rn(v - shift);
+    __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, h),
+                                reinterpret_cast<unsigned short*>(p) + k);
+#else
     p[k] = __float2half_rn(v - shift);
+#endif
   }
   static __device__ __forceinline__ float roundtrip(float v, float shift) {
     return __half2float(__float2half_rn(v - shift)) + shift;

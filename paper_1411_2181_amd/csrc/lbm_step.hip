@@ -43,28 +43,24 @@ __device__ __forceinline__ int64_t nid(int x, int y, int z, int nx, int ny) {
   return ((int64_t)z * ny + y) * nx + x;
 }
 
-// Polymer stress T_k at node k (component order xx yy zz xy xz yz).
-template <typename T>
-__device__ __forceinline__ void stress_at(const T* __restrict__ C, const T* __restrict__ rho,
-                                          int64_t N, int64_t k, const RunDev& R, T out[6]) {
-  const T rA = rho[k], rB = rho[N + k];
-  const T rp = R.visc == 0 ? rA : rB;
-  T chi = (rp / (rA + rB) - T(R.chi_lo)) * T(R.inv_chi_range);
-  chi = chi < T(0) ? T(0) : (chi > T(1) ? T(1) : chi);
-  T c[6];
-#pragma unroll
-  for (int m = 0; m < 6; ++m) c[m] = C[m * N + k];
-  const double tr = (double)c[0] + (double)c[1] + (double)c[2];
-  const T fP = (T)((R.L2 - 3.0) / (R.L2 - tr));
-  const T coef = chi * T(R.etaP_over_tauP);
-#pragma unroll
-  for (int m = 0; m < 6; ++m) out[m] = coef * (fP * c[m] - (m < 3 ? T(1) : T(0)));
-}
+// Shapes of the tile (bx, by) with a compiled instance of every pass.
+#define LBM_FOR_SHAPES(M) M(64, 4) M(32, 8) M(128, 2) M(64, 2) M(32, 4)
 
 // ---- force pass ----------------------------------------------------------------
-template <typename T, typename S>
-__global__ void __launch_bounds__(256) k_force(StepArgs<T, S> a) {
+// One workgroup marches up the z range of a bx*by tile.  The densities (and,
+// for a viscoelastic run, the polymer stress T computed once per node) of
+// planes z-1, z, z+1 of the tile plus a one-node halo live in an LDS ring;
+// the raw values of plane z+2 are loaded into registers while plane z is
+// computed.  Ghost planes beyond the walls repeat the boundary plane (mirror
+// density, zero-gradient C, hence the same T).
+template <typename T, typename S, int BX, int BY>
+__global__ void __launch_bounds__(BX * BY) k_force(StepArgs<T, S> a) {
+  constexpr int HX = BX + 2, HY = BY + 2, HN = HX * HY, NT = BX * BY;
+  constexpr int KP = (HN + NT - 1) / NT;
+  __shared__ T srho[4][2][HN];
+  __shared__ T sT[4][6][HN];
   const int g = *a.gstep;
+  const int tx = (int)threadIdx.x, ty = (int)threadIdx.y, tid = ty * BX + tx;
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const Tile tl = a.tiles[t];
     if (tl.run < 0) continue;
@@ -72,8 +68,9 @@ __global__ void __launch_bounds__(256) k_force(StepArgs<T, S> a) {
     if (g >= R.target) continue;
     const int par = (R.base + g) & 1;
     const int nx = R.nx, ny = R.ny, nz = R.nz;
-    const int x = tl.x0 + (int)threadIdx.x, y = tl.y0 + (int)threadIdx.y;
-    if (x >= nx || y >= ny) continue;
+    const int x = tl.x0 + tx, y = tl.y0 + ty;
+    const bool active = x < nx && y < ny;
+    const bool visc = R.visc >= 0;
     const int64_t N = R.ld;   // stride between the component arrays of a field
     const T* __restrict__ rho = a.P.rho[par] + 2 * R.off;
     const T* __restrict__ J = a.P.j[par] + 6 * R.off;
@@ -81,47 +78,102 @@ __global__ void __launch_bounds__(256) k_force(StepArgs<T, S> a) {
     V4<T>* __restrict__ recA = a.P.recA + R.off;
     V4<T>* __restrict__ recB = a.P.recB + R.off;
     T* __restrict__ U = a.P.u + 3 * R.off;
-    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
     const T G = T(R.G);
     const T tA = T(R.tau[0]), tB = T(R.tau[1]);
     const T itA = T(R.inv_tau[0]), itB = T(R.inv_tau[1]);
+    T raw[KP][8];
+    auto load_raw = [&](int zp) {
+      const int zc = zp < 0 ? 0 : (zp >= nz ? nz - 1 : zp);
+#pragma unroll
+      for (int kk = 0; kk < KP; ++kk) {
+        const int k = tid + kk * NT;
+        if (k < HN) {
+          int gx = (tl.x0 + k % HX - 1) % nx;
+          int gy = (tl.y0 + k / HX - 1) % ny;
+          gx += gx < 0 ? nx : 0;
+          gy += gy < 0 ? ny : 0;
+          const int64_t m = nid(gx, gy, zc, nx, ny);
+          raw[kk][0] = rho[m];
+          raw[kk][1] = rho[N + m];
+          if (visc) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) raw[kk][2 + c] = C[c * N + m];
+          }
+        }
+      }
+    };
+    // T = chi (eta_P/tau_P)(f C - I): chi the clamped rescaled mass fraction
+    // of the polymer phase's component, f the Peterlin factor in FP64
+    auto store_raw = [&](int zp) {
+      const int sl = zp & 3;
+#pragma unroll
+      for (int kk = 0; kk < KP; ++kk) {
+        const int k = tid + kk * NT;
+        if (k < HN) {
+          const T rA = raw[kk][0], rB = raw[kk][1];
+          srho[sl][0][k] = rA;
+          srho[sl][1][k] = rB;
+          if (visc) {
+            const T rp = R.visc == 0 ? rA : rB;
+            T chi = (rp / (rA + rB) - T(R.chi_lo)) * T(R.inv_chi_range);
+            chi = chi < T(0) ? T(0) : (chi > T(1) ? T(1) : chi);
+            const double tr = (double)raw[kk][2] + (double)raw[kk][3] + (double)raw[kk][4];
+            const T fP = (T)((R.L2 - 3.0) / (R.L2 - tr));
+            const T coef = chi * T(R.etaP_over_tauP);
+#pragma unroll
+            for (int c = 0; c < 6; ++c)
+              sT[sl][c][k] = coef * (fP * raw[kk][2 + c] - (c < 3 ? T(1) : T(0)));
+          }
+        }
+      }
+    };
+    __syncthreads();   // the previous tile's readers are done with the ring
     const int zend = min(tl.z0 + a.bz, nz);
+    load_raw(tl.z0 - 1);
+    store_raw(tl.z0 - 1);
+    load_raw(tl.z0);
+    store_raw(tl.z0);
+    load_raw(tl.z0 + 1);
+    const int lc = (ty + 1) * HX + (tx + 1);
     for (int z = tl.z0; z < zend; ++z) {
-      const int zm = z > 0 ? z - 1 : 0, zp = z < nz - 1 ? z + 1 : nz - 1;
-      const int64_t n = nid(x, y, z, nx, ny);
+      store_raw(z + 1);
+      if (z + 2 <= zend) load_raw(z + 2);
+      const int64_t n = nid(active ? x : 0, active ? y : 0, z, nx, ny);
+      T jA0 = 0, jA1 = 0, jA2 = 0, jB0 = 0, jB1 = 0, jB2 = 0;
+      if (active) {
+        jA0 = J[n]; jA1 = J[N + n]; jA2 = J[2 * N + n];
+        jB0 = J[3 * N + n]; jB1 = J[4 * N + n]; jB2 = J[5 * N + n];
+      }
+      __syncthreads();
+      if (!active) continue;
       // Shan-Chen: F_A = -G rho_A sum_i 3 w_i rho_B(x+c_i) c_i (and A<->B)
       T sA0 = 0, sA1 = 0, sA2 = 0, sB0 = 0, sB1 = 0, sB2 = 0;
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
-        const int xx = CX[i] > 0 ? xp : (CX[i] < 0 ? xm : x);
-        const int yy = CY[i] > 0 ? yp : (CY[i] < 0 ? ym : y);
-        const int zz = CZ[i] > 0 ? zp : (CZ[i] < 0 ? zm : z);
-        const int64_t k = nid(xx, yy, zz, nx, ny);
-        const T nA = rho[k], nB = rho[N + k];
+        const int sl = (z + CZ[i]) & 3;
+        const int k = lc + CY[i] * HX + CX[i];
+        const T nA = srho[sl][0][k], nB = srho[sl][1][k];
         const T wt = T(3) * wgt<T>(i);
         if (CX[i] != 0) { sA0 += (wt * T(CX[i])) * nB; sB0 += (wt * T(CX[i])) * nA; }
         if (CY[i] != 0) { sA1 += (wt * T(CY[i])) * nB; sB1 += (wt * T(CY[i])) * nA; }
         if (CZ[i] != 0) { sA2 += (wt * T(CZ[i])) * nB; sB2 += (wt * T(CZ[i])) * nA; }
       }
-      const T rA = rho[n], rB = rho[N + n];
+      const int s0 = z & 3, sp = (z + 1) & 3, sm = (z - 1) & 3;
+      const T rA = srho[s0][0][lc], rB = srho[s0][1][lc];
       T FA0 = -G * rA * sA0, FA1 = -G * rA * sA1, FA2 = -G * rA * sA2;
       T FB0 = -G * rB * sB0, FB1 = -G * rB * sB1, FB2 = -G * rB * sB2;
-      if (R.visc >= 0) {
-        T tp[6], tm[6];
+      if (visc) {
+        // F^P_a = sum_b [T_ab(x+e_b) - T_ab(x-e_b)]/2
+        const T dx0 = T(0.5) * (sT[s0][0][lc + 1] - sT[s0][0][lc - 1]);
+        const T dx1 = T(0.5) * (sT[s0][3][lc + 1] - sT[s0][3][lc - 1]);
+        const T dx2 = T(0.5) * (sT[s0][4][lc + 1] - sT[s0][4][lc - 1]);
+        const T dy0 = T(0.5) * (sT[s0][3][lc + HX] - sT[s0][3][lc - HX]);
+        const T dy1 = T(0.5) * (sT[s0][1][lc + HX] - sT[s0][1][lc - HX]);
+        const T dy2 = T(0.5) * (sT[s0][5][lc + HX] - sT[s0][5][lc - HX]);
+        const T dz0 = T(0.5) * (sT[sp][4][lc] - sT[sm][4][lc]);
+        const T dz1 = T(0.5) * (sT[sp][5][lc] - sT[sm][5][lc]);
+        const T dz2 = T(0.5) * (sT[sp][2][lc] - sT[sm][2][lc]);
         T P0 = 0, P1 = 0, P2 = 0;
-        // b = x
-        stress_at(C, rho, N, nid(xp, y, z, nx, ny), R, tp);
-        stress_at(C, rho, N, nid(xm, y, z, nx, ny), R, tm);
-        const T dx0 = T(0.5) * (tp[0] - tm[0]), dx1 = T(0.5) * (tp[3] - tm[3]), dx2 = T(0.5) * (tp[4] - tm[4]);
-        // b = y
-        stress_at(C, rho, N, nid(x, yp, z, nx, ny), R, tp);
-        stress_at(C, rho, N, nid(x, ym, z, nx, ny), R, tm);
-        const T dy0 = T(0.5) * (tp[3] - tm[3]), dy1 = T(0.5) * (tp[1] - tm[1]), dy2 = T(0.5) * (tp[5] - tm[5]);
-        // b = z (ghost planes repeat the boundary plane)
-        stress_at(C, rho, N, nid(x, y, zp, nx, ny), R, tp);
-        stress_at(C, rho, N, nid(x, y, zm, nx, ny), R, tm);
-        const T dz0 = T(0.5) * (tp[4] - tm[4]), dz1 = T(0.5) * (tp[5] - tm[5]), dz2 = T(0.5) * (tp[2] - tm[2]);
         P0 = ((P0 + dx0) + dy0) + dz0;
         P1 = ((P1 + dx1) + dy1) + dz1;
         P2 = ((P2 + dx2) + dy2) + dz2;
@@ -130,8 +182,6 @@ __global__ void __launch_bounds__(256) k_force(StepArgs<T, S> a) {
         FA0 = FA0 + fa * P0; FA1 = FA1 + fa * P1; FA2 = FA2 + fa * P2;
         FB0 = FB0 + fb * P0; FB1 = FB1 + fb * P1; FB2 = FB2 + fb * P2;
       }
-      const T jA0 = J[n], jA1 = J[N + n], jA2 = J[2 * N + n];
-      const T jB0 = J[3 * N + n], jB1 = J[4 * N + n], jB2 = J[5 * N + n];
       const T den = rA * itA + rB * itB;
       const T up0 = (jA0 * itA + jB0 * itB) / den;
       const T up1 = (jA1 * itA + jB1 * itB) / den;
@@ -194,58 +244,89 @@ __global__ void __launch_bounds__(BX * BY) k_collide(StepArgs<T, S> a) {
         sl[k] = rec[nid(gx, gy, zp, nx, ny)];
       }
     };
+    // the populations that arrive at (x, y, zz): pulled from x - c_i, or the
+    // node's own opposite population where the link crosses a wall
+    auto load_plane = [&](int zz, T (&v)[Q]) {
+      const int64_t m = nid(x, y, zz, nx, ny);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int zs = zz - CZ[i];
+        if (CZ[i] == 0 || (zs >= 0 && zs < nz)) {
+          const int xs = CX[i] > 0 ? xm : (CX[i] < 0 ? xp : x);
+          const int ys = CY[i] > 0 ? ym : (CY[i] < 0 ? yp : y);
+          v[i] = Store<T, S>::load(fs + (int64_t)i * N, nid(xs, ys, zs, nx, ny), wgt<T>(i) * r0);
+        } else {
+          const int o = OPPI[i];
+          v[i] = Store<T, S>::load(fs + (int64_t)o * N, m, wgt<T>(o) * r0);
+        }
+      }
+    };
     __syncthreads();   // the previous tile's readers are done with the ring
     const int zend = min(tl.z0 + a.bz, nz);
     if (tl.z0 > 0) stage(tl.z0 - 1);
     stage(tl.z0);
+    // software pipeline: the populations of plane z+1 are in flight while
+    // plane z is collided
+    T cur[Q];
+    if (active) load_plane(tl.z0, cur);
     for (int z = tl.z0; z < zend; ++z) {
+      T nxt[Q];
+      if (active && z + 1 < zend) load_plane(z + 1, nxt);
       if (z + 1 < nz) stage(z + 1);
       __syncthreads();
-      if (!active) continue;
-      const int64_t n = nid(x, y, z, nx, ny);
-      const int lc = (ty + 1) * HX + (tx + 1);
-      T rsum = 0, jx = 0, jy = 0, jz = 0;
+      if (active) {
+        const int64_t n = nid(x, y, z, nx, ny);
+        const int lc = (ty + 1) * HX + (tx + 1);
+        T rsum = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        T fpost;
-        const int zs = z - CZ[i];
-        if (CZ[i] == 0 || (zs >= 0 && zs < nz)) {
-          const int xs = CX[i] > 0 ? xm : (CX[i] < 0 ? xp : x);
-          const int ys = CY[i] > 0 ? ym : (CY[i] < 0 ? yp : y);
-          const T fi = Store<T, S>::load(fs + (int64_t)i * N, nid(xs, ys, zs, nx, ny), wgt<T>(i) * r0);
-          const V4<T> r = ring[zs & 3][lc - CY[i] * HX - CX[i]];
-          fpost = fi - (fi - feq<T>(i, r.x, r.y, r.z, r.w)) * it;
-        } else {
-          // half-way bounce-back: the population that left x in direction
-          // opp(i) is reflected by the wall it crossed
-          const int o = OPPI[i];
-          const T fv = Store<T, S>::load(fs + (int64_t)o * N, n, wgt<T>(o) * r0);
-          const V4<T> r = ring[z & 3][lc];
-          const T uwall = CZ[o] > 0 ? uw : -uw;
-          fpost = fv - (fv - feq<T>(o, r.x, r.y, r.z, r.w)) * it
-                  - ((T(6) * wgt<T>(o)) * r.x) * (T(CX[o]) * uwall);
+        for (int i = 0; i < Q; ++i) {
+          T fpost;
+          const int zs = z - CZ[i];
+          if (CZ[i] == 0 || (zs >= 0 && zs < nz)) {
+            const V4<T> r = ring[zs & 3][lc - CY[i] * HX - CX[i]];
+            fpost = cur[i] - (cur[i] - feq<T>(i, r.x, r.y, r.z, r.w)) * it;
+          } else {
+            // half-way bounce-back: the population that left x in direction
+            // opp(i) is reflected by the wall it crossed
+            const int o = OPPI[i];
+            const V4<T> r = ring[z & 3][lc];
+            const T uwall = CZ[o] > 0 ? uw : -uw;
+            fpost = cur[i] - (cur[i] - feq<T>(o, r.x, r.y, r.z, r.w)) * it
+                    - ((T(6) * wgt<T>(o)) * r.x) * (T(CX[o]) * uwall);
+          }
+          Store<T, S>::store(fo + (int64_t)i * N, n, fpost, wgt<T>(i) * r0);
+          // moments of the value as stored (FP16S re-reads its rounding)
+          const T fq = Store<T, S>::roundtrip(fpost, wgt<T>(i) * r0);
+          rsum += fq;
+          if (CX[i] != 0) jx += T(CX[i]) * fq;
+          if (CY[i] != 0) jy += T(CY[i]) * fq;
+          if (CZ[i] != 0) jz += T(CZ[i]) * fq;
         }
-        Store<T, S>::store(fo + (int64_t)i * N, n, fpost, wgt<T>(i) * r0);
-        // moments of the value as stored (FP16S re-reads its rounding)
-        const T fq = Store<T, S>::roundtrip(fpost, wgt<T>(i) * r0);
-        rsum += fq;
-        if (CX[i] != 0) jx += T(CX[i]) * fq;
-        if (CY[i] != 0) jy += T(CY[i]) * fq;
-        if (CZ[i] != 0) jz += T(CZ[i]) * fq;
+        rho_out[n] = rsum;
+        j_out[n] = jx;
+        j_out[N + n] = jy;
+        j_out[2 * N + n] = jz;
+        if (!isfinite(rsum + jx + jy + jz)) atomicOr(a.P.status + tl.run, ST_NAN);
       }
-      rho_out[n] = rsum;
-      j_out[n] = jx;
-      j_out[N + n] = jy;
-      j_out[2 * N + n] = jz;
-      if (!isfinite(rsum + jx + jy + jz)) atomicOr(a.P.status + tl.run, ST_NAN);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
     }
   }
 }
 
 // ---- FENE-P pass -------------------------------------------------------------------
-template <typename T, typename S>
-__global__ void __launch_bounds__(256) k_fene(StepArgs<T, S> a) {
+// Same z-march as the force pass: C and u of planes z-1, z, z+1 (+ halo) in an
+// LDS ring, plane z+2 loaded into registers while plane z is updated.  Ghost
+// planes: C zero-gradient; u extrapolated through the wall velocity,
+// u(-1) = 2 u_bot - u(0), u(nz) = 2 u_top - u(nz-1), u_wall = (-+U_w, 0, 0).
+template <typename T, typename S, int BX, int BY>
+__global__ void __launch_bounds__(BX * BY) k_fene(StepArgs<T, S> a) {
+  constexpr int HX = BX + 2, HY = BY + 2, HN = HX * HY, NT = BX * BY;
+  constexpr int KP = (HN + NT - 1) / NT;
+  __shared__ T sC[4][6][HN];
+  __shared__ T sU[4][3][HN];
   const int g = *a.gstep;
+  const int tx = (int)threadIdx.x, ty = (int)threadIdx.y, tid = ty * BX + tx;
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const Tile tl = a.tiles[t];
     if (tl.run < 0) continue;
@@ -253,42 +334,83 @@ __global__ void __launch_bounds__(256) k_fene(StepArgs<T, S> a) {
     if (g >= R.target || R.visc < 0) continue;
     const int par = (R.base + g) & 1;
     const int nx = R.nx, ny = R.ny, nz = R.nz;
-    const int x = tl.x0 + (int)threadIdx.x, y = tl.y0 + (int)threadIdx.y;
-    if (x >= nx || y >= ny) continue;
+    const int x = tl.x0 + tx, y = tl.y0 + ty;
+    const bool active = x < nx && y < ny;
     const int64_t N = R.ld;   // stride between the component arrays of a field
     const T* __restrict__ Cin = a.P.C[par] + 6 * R.off;
     T* __restrict__ Cout = a.P.C[par ^ 1] + 6 * R.off;
     const T* __restrict__ U = a.P.u + 3 * R.off;
-    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
     const T uw = T(R.u_wall);
     const T itP = T(R.inv_tauP);
+    T raw[KP][9];
+    auto load_raw = [&](int zp) {
+      const int zc = zp < 0 ? 0 : (zp >= nz ? nz - 1 : zp);
+#pragma unroll
+      for (int kk = 0; kk < KP; ++kk) {
+        const int k = tid + kk * NT;
+        if (k < HN) {
+          int gx = (tl.x0 + k % HX - 1) % nx;
+          int gy = (tl.y0 + k / HX - 1) % ny;
+          gx += gx < 0 ? nx : 0;
+          gy += gy < 0 ? ny : 0;
+          const int64_t m = nid(gx, gy, zc, nx, ny);
+#pragma unroll
+          for (int c = 0; c < 6; ++c) raw[kk][c] = Cin[c * N + m];
+#pragma unroll
+          for (int b = 0; b < 3; ++b) raw[kk][6 + b] = U[b * N + m];
+        }
+      }
+    };
+    auto store_raw = [&](int zp) {
+      const int sl = zp & 3;
+#pragma unroll
+      for (int kk = 0; kk < KP; ++kk) {
+        const int k = tid + kk * NT;
+        if (k < HN) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) sC[sl][c][k] = raw[kk][c];
+          if (zp < 0) {
+            sU[sl][0][k] = T(2) * (-uw) - raw[kk][6];
+            sU[sl][1][k] = T(2) * T(0) - raw[kk][7];
+            sU[sl][2][k] = T(2) * T(0) - raw[kk][8];
+          } else if (zp >= nz) {
+            sU[sl][0][k] = T(2) * uw - raw[kk][6];
+            sU[sl][1][k] = T(2) * T(0) - raw[kk][7];
+            sU[sl][2][k] = T(2) * T(0) - raw[kk][8];
+          } else {
+#pragma unroll
+            for (int b = 0; b < 3; ++b) sU[sl][b][k] = raw[kk][6 + b];
+          }
+        }
+      }
+    };
+    __syncthreads();   // the previous tile's readers are done with the ring
     const int zend = min(tl.z0 + a.bz, nz);
+    load_raw(tl.z0 - 1);
+    store_raw(tl.z0 - 1);
+    load_raw(tl.z0);
+    store_raw(tl.z0);
+    load_raw(tl.z0 + 1);
+    const int lc = (ty + 1) * HX + (tx + 1);
     uint32_t st = 0;
     for (int z = tl.z0; z < zend; ++z) {
+      store_raw(z + 1);
+      if (z + 2 <= zend) load_raw(z + 2);
+      __syncthreads();
+      if (!active) continue;
       const int64_t n = nid(x, y, z, nx, ny);
-      const int zm = z > 0 ? z - 1 : 0, zp = z < nz - 1 ? z + 1 : nz - 1;
-      const int64_t nxm = nid(xm, y, z, nx, ny), nxp = nid(xp, y, z, nx, ny);
-      const int64_t nym = nid(x, ym, z, nx, ny), nyp = nid(x, yp, z, nx, ny);
-      const int64_t nzm = nid(x, y, zm, nx, ny), nzp = nid(x, y, zp, nx, ny);
-      const T u0 = U[n], u1 = U[N + n], u2 = U[2 * N + n];
-      // velocity of the face neighbours; beyond a wall the ghost value
-      // extrapolates linearly through the wall velocity (+-U_w, 0, 0)
-      T uzp[3], uzm[3];
-      if (z < nz - 1) { uzp[0] = U[nzp]; uzp[1] = U[N + nzp]; uzp[2] = U[2 * N + nzp]; }
-      else { uzp[0] = T(2) * uw - u0; uzp[1] = T(2) * T(0) - u1; uzp[2] = T(2) * T(0) - u2; }
-      if (z > 0) { uzm[0] = U[nzm]; uzm[1] = U[N + nzm]; uzm[2] = U[2 * N + nzm]; }
-      else { uzm[0] = T(2) * (-uw) - u0; uzm[1] = T(2) * T(0) - u1; uzm[2] = T(2) * T(0) - u2; }
+      const int s0 = z & 3, sp = (z + 1) & 3, sm = (z - 1) & 3;
+      const T u0 = sU[s0][0][lc], u1 = sU[s0][1][lc], u2 = sU[s0][2][lc];
       T Gm[3][3];
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        Gm[0][b] = T(0.5) * (U[b * N + nxp] - U[b * N + nxm]);
-        Gm[1][b] = T(0.5) * (U[b * N + nyp] - U[b * N + nym]);
-        Gm[2][b] = T(0.5) * (uzp[b] - uzm[b]);
+        Gm[0][b] = T(0.5) * (sU[s0][b][lc + 1] - sU[s0][b][lc - 1]);
+        Gm[1][b] = T(0.5) * (sU[s0][b][lc + HX] - sU[s0][b][lc - HX]);
+        Gm[2][b] = T(0.5) * (sU[sp][b][lc] - sU[sm][b][lc]);
       }
       T c[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) c[k] = Cin[k * N + n];
+      for (int k = 0; k < 6; ++k) c[k] = sC[s0][k][lc];
       const double tr = (double)c[0] + (double)c[1] + (double)c[2];
       if (tr >= R.L2) st |= ST_FENE;
       const T fP = (T)((R.L2 - 3.0) / (R.L2 - tr));
@@ -303,9 +425,9 @@ __global__ void __launch_bounds__(256) k_fene(StepArgs<T, S> a) {
       for (int k = 0; k < 6; ++k) {
         const T ck = c[k];
         T adv = 0;
-        adv += ua0 * (ck - Cin[k * N + nxm]) + ub0 * (Cin[k * N + nxp] - ck);
-        adv += ua1 * (ck - Cin[k * N + nym]) + ub1 * (Cin[k * N + nyp] - ck);
-        adv += ua2 * (ck - Cin[k * N + nzm]) + ub2 * (Cin[k * N + nzp] - ck);
+        adv += ua0 * (ck - sC[s0][k][lc - 1]) + ub0 * (sC[s0][k][lc + 1] - ck);
+        adv += ua1 * (ck - sC[s0][k][lc - HX]) + ub1 * (sC[s0][k][lc + HX] - ck);
+        adv += ua2 * (ck - sC[sm][k][lc]) + ub2 * (sC[sp][k][lc] - ck);
         T Sk = 0;
 #pragma unroll
         for (int m = 0; m < 3; ++m)
@@ -324,22 +446,31 @@ __global__ void __launch_bounds__(256) k_fene(StepArgs<T, S> a) {
 // ---- host launchers ------------------------------------------------------------------
 template <typename T, typename S>
 void launch_force(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s) {
-  k_force<T, S><<<grid, block, 0, s>>>(a);
+#define FORCE_CASE(BX, BY) \
+  else if (block.x == BX && block.y == BY) k_force<T, S, BX, BY><<<grid, block, 0, s>>>(a);
+  if (false) {}
+  LBM_FOR_SHAPES(FORCE_CASE)
+#undef FORCE_CASE
 }
 
 template <typename T, typename S>
 void launch_collide(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s) {
   const dim3 g2(grid.x, 2);
-  if (block.x == 64 && block.y == 4) k_collide<T, S, 64, 4><<<g2, block, 0, s>>>(a);
-  else if (block.x == 32 && block.y == 8) k_collide<T, S, 32, 8><<<g2, block, 0, s>>>(a);
-  else if (block.x == 128 && block.y == 2) k_collide<T, S, 128, 2><<<g2, block, 0, s>>>(a);
-  else if (block.x == 64 && block.y == 2) k_collide<T, S, 64, 2><<<g2, block, 0, s>>>(a);
-  else if (block.x == 32 && block.y == 4) k_collide<T, S, 32, 4><<<g2, block, 0, s>>>(a);
+#define COLLIDE_CASE(BX, BY) \
+  else if (block.x == BX && block.y == BY) k_collide<T, S, BX, BY><<<g2, block, 0, s>>>(a);
+  if (false) {}
+  LBM_FOR_SHAPES(COLLIDE_CASE)
+#undef COLLIDE_CASE
 }
 
 template <typename T, typename S>
 void launch_fene(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s) {
-  if (a.any_visc) k_fene<T, S><<<grid, block, 0, s>>>(a);
+  if (!a.any_visc) return;
+#define FENE_CASE(BX, BY) \
+  else if (block.x == BX && block.y == BY) k_fene<T, S, BX, BY><<<grid, block, 0, s>>>(a);
+  if (false) {}
+  LBM_FOR_SHAPES(FENE_CASE)
+#undef FENE_CASE
 }
 
 #define LBM_INST(T, S)                                                                        \

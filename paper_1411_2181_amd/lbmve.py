@@ -14,7 +14,7 @@ from typing import Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblbmve.so")
+LIB_PATH = os.environ.get("LBMVE_LIB", os.path.join(_HERE, "liblbmve.so"))
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSUP, LBM_ENAN, LBM_EFENE = 0, -1, -2, -3, -4, -5, -6
 PRECISION = {"fp64": 0, "fp32": 1, "fp16s": 2}
