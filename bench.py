@@ -102,6 +102,26 @@ def gpu_run(precision, steps, warmup, tune=True):
                 info=info, launch=launch, tuned=tuned)
 
 
+def pmc_pass(precision, steps=4):
+    """Short run for hardware-counter collection: a 1 GiB device-to-device copy
+    (the reference of known size for scaling FETCH_SIZE / WRITE_SIZE), then a
+    few eager steps of the workload with every pass as its own dispatch."""
+    import torch
+    from paper_1411_2181_amd import autotune, lbmve
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    flush = torch.empty_like(a)
+    flush.fill_(2.0)       # evict a from the last-level cache
+    b.copy_(a)             # 1 GiB read + 1 GiB written
+    torch.cuda.synchronize()
+    del a, b, flush
+    p, _ = workload_params()
+    s = lbmve.Solver(p, precision)
+    autotune.tune(s, steps=2, use_cache=False, save=False)
+    s.step_profiled(steps)
+    s.close()
+
+
 def cpu_baseline(seconds=12.0):
     """The FP64 oracle on a bounded sample of the same workload: the same
     physics on a 96x72x128 sub-box (full gap, R = 32 droplet), timed on one
@@ -133,6 +153,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16s"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--variants", default="fp16s", help="extra storage precisions to report")
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="short run for rocprofv3 counter collection (prints no JSON)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; "
@@ -140,6 +162,9 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
+    if args.pmc_pass:
+        pmc_pass(args.precision)
+        return
 
     r = gpu_run(args.precision, args.steps, args.warmup)
     nodes, wall = r["nodes"], r["wall"]

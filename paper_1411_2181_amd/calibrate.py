@@ -26,7 +26,8 @@ from . import lbmve, physics
 # (G, relaxation times) groups; with the velocity-shift forcing the droplet
 # is Laplace-consistent only for tau of about 1..1.5 at G = 0.9 (beyond that
 # the minority densities drift with tau and droplets dissolve or distort)
-GROUPS = ((0.9, (1.0, 1.25, 1.5, 1.75)),)
+GROUPS = ((0.9, (1.0, 1.25, 1.5, 1.75)), (0.75, (1.0, 1.25, 1.5, 1.75)),
+          (0.8, (1.0, 1.25, 1.5)))
 RADII = (10.0, 12.0, 14.0)
 BOX = 48
 STEPS = 4000

@@ -104,6 +104,19 @@ _SIGNATURES = {
     "lbm_batch_import": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.c_size_t]),
     "lbm_batch_nruns": (ctypes.c_int32, [ctypes.c_void_p]),
+    "sg_param_count": (ctypes.c_int32, []),
+    "sg_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "sg_init": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                               ctypes.POINTER(ctypes.c_void_p)]),
+    "sg_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "sg_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "sg_get_working_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "sg_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "sg_gradient": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
+    "sg_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_int32, ctypes.c_float, ctypes.POINTER(ctypes.c_float)]),
+    "sg_destroy": (None, [ctypes.c_void_p]),
 }
 
 
@@ -275,3 +288,67 @@ class Solver(Batch):
 
     def observe(self, components: bool = False, check: bool = False) -> dict:
         return super().observe(components, check)[0]
+
+
+class Network:
+    """The surrogate network's device state (sg_* calls).  Inputs and targets
+    are float32 torch tensors on the context's device."""
+
+    def __init__(self, batch_max: int, device="cuda:0", stream=None):
+        import torch
+        L = lib()
+        self.batch_max = int(batch_max)
+        self.n_params = int(L.sg_param_count())
+        nbytes = ctypes.c_size_t()
+        _check(L.sg_workspace_bytes(self.batch_max, ctypes.byref(nbytes)), "sg workspace")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        _check(L.sg_init(self.batch_max, ctypes.c_void_p(self.workspace.data_ptr()), nbytes.value,
+                         ctypes.c_void_p(_stream_ptr(self.stream)), ctypes.byref(ctx)), "sg init")
+        self._ctx = ctx
+
+    def set_params(self, p: np.ndarray):
+        v = np.ascontiguousarray(p, dtype=np.float32)
+        _check(lib().sg_set_params(self._ctx, v.ctypes.data, v.size), "sg set_params")
+
+    def params(self, working: bool = False) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        fn = lib().sg_get_working_params if working else lib().sg_get_params
+        _check(fn(self._ctx, out.ctypes.data, out.size), "sg get_params")
+        return out
+
+    def forward(self, x):
+        import torch
+        z = torch.empty((x.shape[0], 3), dtype=torch.float32, device=self.device)
+        _check(lib().sg_forward(self._ctx, ctypes.c_void_p(x.data_ptr()), int(x.shape[0]),
+                                ctypes.c_void_p(z.data_ptr())), "sg forward")
+        return z
+
+    def gradient(self, x, t, m):
+        g = np.empty(self.n_params, dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(lib().sg_gradient(self._ctx, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                 ctypes.c_void_p(m.data_ptr()), int(x.shape[0]), g.ctypes.data,
+                                 ctypes.byref(loss)), "sg gradient")
+        return g, float(loss.value)
+
+    def train_step(self, x, t, m, lr: float) -> float:
+        loss = ctypes.c_float()
+        _check(lib().sg_train_step(self._ctx, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                   ctypes.c_void_p(m.data_ptr()), int(x.shape[0]), float(lr),
+                                   ctypes.byref(loss)), "sg train_step")
+        return float(loss.value)
+
+    def close(self):
+        if self._ctx is not None and self._ctx.value:
+            lib().sg_destroy(self._ctx)
+        self._ctx = None
+        self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
