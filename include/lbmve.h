@@ -60,8 +60,9 @@ enum {
 enum {
   LBM_FP64 = 0,   /* populations FP64, C FP64, arithmetic FP64                */
   LBM_FP32 = 1,   /* populations FP32, C FP32, arithmetic FP32                */
-  LBM_FP16S = 2   /* populations FP16 stored as f - w_i rho0_s, C FP32,
-                     arithmetic FP32                                          */
+  LBM_FP16S = 2   /* populations FP16 stored as f_i - w_i rho_s(x), the
+                     shift taken from the FP32 density of the node holding
+                     the value; C FP32, arithmetic FP32                       */
 };
 /* In every precision the Peterlin factor f(tr C) and all observable
  * reductions are evaluated in FP64. */
@@ -102,7 +103,6 @@ typedef struct {
                             x_p the mass fraction of the polymer phase's
                             component; both 0 => mean-field coexistence
                             fractions at (G, rho_major + rho_minor)          */
-  double rho0[2];        /* FP16S shift densities of A and B (0 => rho_major)*/
 } lbm_params;
 
 /* Observables of one run at the current state. */
@@ -154,8 +154,13 @@ int lbm_step(lbm_ctx* ctx, int32_t nsteps);
  * run's status word is set (out is still filled). */
 int lbm_observe(lbm_ctx* ctx, int32_t want_components, lbm_obs* out);
 /* Copy a field of run 0 to / from a host FP64 buffer of n elements (the
- * exact element count of the field, else LBM_EINVAL); synchronises.  Import
- * of LBM_FIELD_F recomputes the moment fields; status is cleared on import. */
+ * exact element count of the field, else LBM_EINVAL); synchronises.  Only F
+ * and C can be imported.  Populations are held as g_i = f_i - w_i rho_s(x)
+ * against the node densities: export of F decodes them in FP64; import of F
+ * sets rho_s = sum_i f_i (FP64, rounded to the field type), the shifted
+ * values against it and the momenta.  Status is cleared on import.  An F
+ * export/import round trip is exact up to that rounding; for a bit-exact
+ * restart use lbm_batch_save_state / lbm_batch_load_state. */
 int lbm_export(lbm_ctx* ctx, int32_t field, double* host, size_t n);
 int lbm_import(lbm_ctx* ctx, int32_t field, const double* host, size_t n);
 void lbm_destroy(lbm_ctx* ctx);
@@ -191,6 +196,19 @@ int lbm_batch_export(lbm_ctx* ctx, int32_t run, int32_t field, double* host,
 int lbm_batch_import(lbm_ctx* ctx, int32_t run, int32_t field,
                      const double* host, size_t n);
 int32_t lbm_batch_nruns(const lbm_ctx* ctx);
+
+/* ---- checkpoint / restart ------------------------------------------------
+ * The raw state of one run: populations as stored, node densities and C,
+ * behind a header (precision, box, viscoelastic phase, step count).  A load
+ * restores the run bit for bit, including its step count, into a context of
+ * the same precision whose run has the same box and viscoelastic phase
+ * (else LBM_EINVAL); it recomputes the momenta and clears the run's status.
+ * The host buffer is the caller's; bytes must equal lbm_batch_state_bytes.
+ * Both synchronise the context's stream. */
+int lbm_batch_state_bytes(const lbm_ctx* ctx, int32_t run, size_t* bytes);
+int lbm_batch_save_state(lbm_ctx* ctx, int32_t run, void* host, size_t bytes);
+int lbm_batch_load_state(lbm_ctx* ctx, int32_t run, const void* host,
+                         size_t bytes);
 
 #ifdef __cplusplus
 }

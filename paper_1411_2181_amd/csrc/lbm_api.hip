@@ -210,7 +210,6 @@ int validate(const lbm_params* p) {
   for (int s = 0; s < 2; ++s) {
     if (!(p->tau[s] > 0.5) || !std::isfinite(p->tau[s])) return LBM_EINVAL;
     if (!(p->eta_P[s] >= 0.0) || !std::isfinite(p->eta_P[s])) return LBM_EINVAL;
-    if (!(p->rho0[s] >= 0.0) || !std::isfinite(p->rho0[s])) return LBM_EINVAL;
     if (p->eta_P[s] > 0.0) {
       if (!(p->tau_P[s] > 0.0) || !std::isfinite(p->tau_P[s])) return LBM_EINVAL;
       if (!(p->L2[s] > 3.0)) return LBM_EINVAL;
@@ -249,7 +248,6 @@ RunDev make_run(const lbm_params& p, int64_t off) {
   for (int s = 0; s < 2; ++s) {
     R.tau[s] = p.tau[s];
     R.inv_tau[s] = 1.0 / p.tau[s];
-    R.rho0[s] = p.precision == LBM_FP16S ? (p.rho0[s] > 0.0 ? p.rho0[s] : p.rho_major) : 0.0;
   }
   if (R.visc >= 0) {
     const int v = R.visc;
@@ -323,7 +321,7 @@ int set_targets(lbm_ctx* c, const int32_t* target) {
     Targets t{};
     for (int i = 0; i < count; ++i) {
       t.target[i] = target[first + i];
-      t.base[i] = (int32_t)(c->done[first + i] & 1);
+      t.base[i] = (int32_t)(c->done[first + i] & 0x7fffffff);
       c->runs[first + i].target = t.target[i];
       c->runs[first + i].base = t.base[i];
     }
@@ -687,6 +685,70 @@ static int64_t field_elems(const lbm_params& p, int field) {
   }
 }
 
+}  // extern "C"
+
+namespace {
+
+// Storage units of the shifted populations (FP16 keeps g * 2^12).
+double pop_scale(int prec) { return prec == LBM_FP16S ? 4096.0 : 1.0; }
+
+// Host views of device element types: S (populations) and T (other fields).
+double get_elem(size_t bytes, const char* buf, int64_t k) {
+  if (bytes == 8) return ((const double*)buf)[k];
+  if (bytes == 4) return (double)((const float*)buf)[k];
+  return (double)__half2float(((const __half*)buf)[k]);
+}
+void put_elem(size_t bytes, char* buf, int64_t k, double v) {
+  if (bytes == 8) ((double*)buf)[k] = v;
+  else if (bytes == 4) ((float*)buf)[k] = (float)v;
+  else ((__half*)buf)[k] = __float2half_rn((float)v);
+}
+
+// Device <-> host copies of a run's block of `comps` arrays (stride ld).
+int copy_out(const lbm_ctx* c, size_t dev_off, size_t elem, int comps, const RunDev& R, char* host) {
+  const size_t w = (size_t)R.n * elem;
+  return hipMemcpy2D(host, w, c->ws + dev_off, (size_t)R.ld * elem, w, comps,
+                     hipMemcpyDeviceToHost) == hipSuccess ? LBM_OK : LBM_EHIP;
+}
+int copy_in(lbm_ctx* c, size_t dev_off, size_t elem, int comps, const RunDev& R, const char* host) {
+  const size_t w = (size_t)R.n * elem;
+  return hipMemcpy2D(c->ws + dev_off, (size_t)R.ld * elem, host, w, w, comps,
+                     hipMemcpyHostToDevice) == hipSuccess ? LBM_OK : LBM_EHIP;
+}
+
+// Momenta of every run at its current parity; clear one run's status.
+int after_state_change(lbm_ctx* c, int run) {
+  std::vector<int32_t> zero(c->nruns, 0);
+  int e = set_targets(c, zero.data());
+  if (e) return e;
+  by_precision(c->prec, [&](auto* ttag, auto* stag) {
+    using T = std::remove_pointer_t<decltype(ttag)>;
+    using S = std::remove_pointer_t<decltype(stag)>;
+    lbm::launch_moments<T, S>(aux_args<T, S>(c, 1), c->stream);
+  });
+  lbm::launch_fill_u32(c->at<uint32_t>(c->L.status) + run, 0u, 1, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+// Raw state blob: header, then populations as stored, densities and C.
+struct StateHeader {
+  uint64_t magic;
+  int32_t precision, nx, ny, nz, visc, pad;
+  int64_t done;
+};
+constexpr uint64_t STATE_MAGIC = 0x31534d564d424cull;   // "LBMVMS1"
+
+size_t state_bytes(const lbm_ctx* c, int run) {
+  const int64_t N = c->runs[run].n;
+  return sizeof(StateHeader) + (size_t)N * (38 * elem_S(c->prec) + 8 * elem_T(c->prec));
+}
+
+}  // namespace
+
+extern "C" {
+
 int lbm_batch_export(lbm_ctx* c, int32_t run, int32_t field, double* host, size_t n) {
   if (!c || !host || run < 0 || run >= c->nruns) return LBM_EINVAL;
   const int64_t want = field_elems(c->prm[run], field);
@@ -700,20 +762,20 @@ int lbm_batch_export(lbm_ctx* c, int32_t run, int32_t field, double* host, size_
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   const size_t st = elem_S(c->prec), tt = elem_T(c->prec);
-  const int64_t LD = R.ld;
   std::vector<char> buf;
+  int e = LBM_OK;
   if (field == LBM_FIELD_F) {
+    // f_i = g_i + w_i rho_s(x), decoded in FP64
+    std::vector<char> rb((size_t)2 * N * tt);
     buf.resize((size_t)want * st);
-    HIPCHK(hipMemcpy2D(buf.data(), N * st, c->ws + c->L.f[par] + (size_t)R.off * 38 * st, LD * st,
-                       N * st, 38, hipMemcpyDeviceToHost));
+    e = copy_out(c, c->L.f[par] + (size_t)R.off * 38 * st, st, 38, R, buf.data());
+    if (!e) e = copy_out(c, c->L.rho[par] + (size_t)R.off * 2 * tt, tt, 2, R, rb.data());
+    if (e) return e;
+    const double isc = 1.0 / pop_scale(c->prec);
     for (int64_t k = 0; k < want; ++k) {
-      if (c->prec == LBM_FP64) host[k] = ((double*)buf.data())[k];
-      else if (c->prec == LBM_FP32) host[k] = ((float*)buf.data())[k];
-      else {
-        const int s = (int)(k / (19 * N)), i = (int)((k / N) % 19);
-        const float shift = lbm::wgt<float>(i) * (float)R.rho0[s];
-        host[k] = (double)(__half2float(((__half*)buf.data())[k]) + shift);
-      }
+      const int s = (int)(k / (19 * N)), i = (int)((k / N) % 19);
+      host[k] = get_elem(st, buf.data(), k) * isc +
+                lbm::wgt<double>(i) * get_elem(tt, rb.data(), s * N + k % N);
     }
     return LBM_OK;
   }
@@ -723,9 +785,9 @@ int lbm_batch_export(lbm_ctx* c, int32_t run, int32_t field, double* host, size_
   else if (field == LBM_FIELD_RHO) { src = c->L.rho[par] + (size_t)R.off * 2 * tt; comps = 2; }
   else { src = c->L.u + (size_t)R.off * 3 * tt; comps = 3; }
   buf.resize((size_t)want * tt);
-  HIPCHK(hipMemcpy2D(buf.data(), N * tt, c->ws + src, LD * tt, N * tt, comps, hipMemcpyDeviceToHost));
-  for (int64_t k = 0; k < want; ++k)
-    host[k] = tt == 8 ? ((double*)buf.data())[k] : (double)((float*)buf.data())[k];
+  e = copy_out(c, src, tt, comps, R, buf.data());
+  if (e) return e;
+  for (int64_t k = 0; k < want; ++k) host[k] = get_elem(tt, buf.data(), k);
   return LBM_OK;
 }
 
@@ -744,43 +806,85 @@ int lbm_batch_import(lbm_ctx* c, int32_t run, int32_t field, const double* host,
   const size_t st = elem_S(c->prec), tt = elem_T(c->prec);
   HIPCHK(hipStreamSynchronize(c->stream));
   std::vector<char> buf;
+  int e = LBM_OK;
   if (field == LBM_FIELD_F) {
-    buf.resize((size_t)want * st);
-    for (int64_t k = 0; k < want; ++k) {
-      if (c->prec == LBM_FP64) ((double*)buf.data())[k] = host[k];
-      else if (c->prec == LBM_FP32) ((float*)buf.data())[k] = (float)host[k];
-      else {
-        const int s = (int)(k / (19 * N)), i = (int)((k / N) % 19);
-        const float shift = lbm::wgt<float>(i) * (float)R.rho0[s];
-        ((__half*)buf.data())[k] = __float2half_rn((float)host[k] - shift);
+    // node densities rho_s = sum_i f_i (FP64, rounded to the field type), then
+    // the shifted values g_i = f_i - w_i rho_s against them
+    std::vector<char> rb((size_t)2 * N * tt);
+    for (int s = 0; s < 2; ++s)
+      for (int64_t m = 0; m < N; ++m) {
+        double r = 0.0;
+        for (int i = 0; i < 19; ++i) r += host[((int64_t)s * 19 + i) * N + m];
+        put_elem(tt, rb.data(), s * N + m, r);
       }
+    buf.resize((size_t)want * st);
+    const double sc = pop_scale(c->prec);
+    for (int64_t k = 0; k < want; ++k) {
+      const int s = (int)(k / (19 * N)), i = (int)((k / N) % 19);
+      put_elem(st, buf.data(), k,
+               (host[k] - lbm::wgt<double>(i) * get_elem(tt, rb.data(), s * N + k % N)) * sc);
     }
-    HIPCHK(hipMemcpy2D(c->ws + c->L.f[par] + (size_t)R.off * 38 * st, R.ld * st, buf.data(), N * st,
-                       N * st, 38, hipMemcpyHostToDevice));
+    e = copy_in(c, c->L.f[par] + (size_t)R.off * 38 * st, st, 38, R, buf.data());
+    if (!e) e = copy_in(c, c->L.rho[par] + (size_t)R.off * 2 * tt, tt, 2, R, rb.data());
   } else {
     buf.resize((size_t)want * tt);
-    for (int64_t k = 0; k < want; ++k) {
-      if (tt == 8) ((double*)buf.data())[k] = host[k];
-      else ((float*)buf.data())[k] = (float)host[k];
-    }
+    for (int64_t k = 0; k < want; ++k) put_elem(tt, buf.data(), k, host[k]);
     // a Newtonian run never updates C, which stays at parity 0
     const int cp = R.visc >= 0 ? par : 0;
-    HIPCHK(hipMemcpy2D(c->ws + c->L.C[cp] + (size_t)R.off * 6 * tt, R.ld * tt, buf.data(), N * tt,
-                       N * tt, 6, hipMemcpyHostToDevice));
+    e = copy_in(c, c->L.C[cp] + (size_t)R.off * 6 * tt, tt, 6, R, buf.data());
   }
-  // moments of every run at its current parity; clear this run's status
-  std::vector<int32_t> zero(c->nruns, 0);
-  int e = set_targets(c, zero.data());
   if (e) return e;
-  by_precision(c->prec, [&](auto* ttag, auto* stag) {
-    using T = std::remove_pointer_t<decltype(ttag)>;
-    using S = std::remove_pointer_t<decltype(stag)>;
-    lbm::launch_moments<T, S>(aux_args<T, S>(c, 1), c->stream);
-  });
-  lbm::launch_fill_u32(c->at<uint32_t>(c->L.status) + run, 0u, 1, c->stream);
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(c->stream));
+  return after_state_change(c, run);
+}
+
+int lbm_batch_state_bytes(const lbm_ctx* c, int32_t run, size_t* bytes) {
+  if (!c || !bytes || run < 0 || run >= c->nruns) return LBM_EINVAL;
+  *bytes = state_bytes(c, run);
   return LBM_OK;
+}
+
+int lbm_batch_save_state(lbm_ctx* c, int32_t run, void* host, size_t bytes) {
+  if (!c || !host || run < 0 || run >= c->nruns || bytes != state_bytes(c, run)) return LBM_EINVAL;
+  const RunDev& R = c->runs[run];
+  const lbm_params& p = c->prm[run];
+  const int par = (int)(c->done[run] & 1);
+  const size_t st = elem_S(c->prec), tt = elem_T(c->prec);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  StateHeader h{STATE_MAGIC, c->prec, p.nx, p.ny, p.nz, R.visc, 0, c->done[run]};
+  char* out = static_cast<char*>(host);
+  std::memcpy(out, &h, sizeof h);
+  char* q = out + sizeof h;
+  int e = copy_out(c, c->L.f[par] + (size_t)R.off * 38 * st, st, 38, R, q);
+  q += (size_t)R.n * 38 * st;
+  if (!e) e = copy_out(c, c->L.rho[par] + (size_t)R.off * 2 * tt, tt, 2, R, q);
+  q += (size_t)R.n * 2 * tt;
+  const int cp = R.visc >= 0 ? par : 0;
+  if (!e) e = copy_out(c, c->L.C[cp] + (size_t)R.off * 6 * tt, tt, 6, R, q);
+  return e;
+}
+
+int lbm_batch_load_state(lbm_ctx* c, int32_t run, const void* host, size_t bytes) {
+  if (!c || !host || run < 0 || run >= c->nruns || bytes != state_bytes(c, run)) return LBM_EINVAL;
+  const RunDev& R = c->runs[run];
+  const lbm_params& p = c->prm[run];
+  StateHeader h;
+  std::memcpy(&h, host, sizeof h);
+  if (h.magic != STATE_MAGIC || h.precision != c->prec || h.nx != p.nx || h.ny != p.ny ||
+      h.nz != p.nz || h.visc != R.visc || h.done < 0)
+    return LBM_EINVAL;
+  const size_t st = elem_S(c->prec), tt = elem_T(c->prec);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->done[run] = h.done;
+  const int par = (int)(h.done & 1);
+  const char* q = static_cast<const char*>(host) + sizeof h;
+  int e = copy_in(c, c->L.f[par] + (size_t)R.off * 38 * st, st, 38, R, q);
+  q += (size_t)R.n * 38 * st;
+  if (!e) e = copy_in(c, c->L.rho[par] + (size_t)R.off * 2 * tt, tt, 2, R, q);
+  q += (size_t)R.n * 2 * tt;
+  const int cp = R.visc >= 0 ? par : 0;
+  if (!e) e = copy_in(c, c->L.C[cp] + (size_t)R.off * 6 * tt, tt, 6, R, q);
+  if (e) return e;
+  return after_state_change(c, run);
 }
 
 int lbm_import(lbm_ctx* c, int32_t field, const double* host, size_t n) {

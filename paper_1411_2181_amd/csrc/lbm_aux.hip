@@ -18,7 +18,8 @@ __device__ __forceinline__ void node_range(int64_t N, int64_t& beg, int64_t& end
 // ---- initial state ----------------------------------------------------------
 // Sphere |x - c|^2 < R^2 (strict) holds rho_A = rho_major, rho_B = rho_minor,
 // the rest the reverse (Section 3: a spherical droplet at mid-gap, shear
-// started from rest); f = w_i rho_s; C = I.  Written at parity 0.
+// started from rest); f = w_i rho_s, i.e. the shifted value g_i = 0 against
+// the node density rho_s; C = I.  Written at parity 0.
 template <typename T, typename S>
 __global__ void k_init(AuxArgs<T, S> a) {
   const int r = blockIdx.y;
@@ -29,7 +30,9 @@ __global__ void k_init(AuxArgs<T, S> a) {
   const double rad = a.radius_centre[4 * r], cx = a.radius_centre[4 * r + 1];
   const double cy = a.radius_centre[4 * r + 2], cz = a.radius_centre[4 * r + 3];
   const double rmaj = a.rho_init[2 * r], rmin = a.rho_init[2 * r + 1];
+  using St = Store<T, S>;
   S* f = a.P.f[0] + 38 * R.off;
+  T* rho = a.P.rho[0] + 2 * R.off;
   T* C = a.P.C[0] + 6 * R.off;
   for (int64_t n = beg + threadIdx.x; n < end; n += blockDim.x) {
     const int x = (int)(n % R.nx);
@@ -40,19 +43,18 @@ __global__ void k_init(AuxArgs<T, S> a) {
     const double rho_s[2] = {inside ? rmaj : rmin, inside ? rmin : rmaj};
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      const T sh = T(R.rho0[s]);
+      rho[s * N + n] = T(rho_s[s]);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const double v = wgt<double>(i) * rho_s[s];
-        Store<T, S>::store(f + ((int64_t)s * Q + i) * N, n, (T)v, wgt<T>(i) * sh);
-      }
+      for (int i = 0; i < Q; ++i) St::store(f + ((int64_t)s * Q + i) * N, n, T(0));
     }
 #pragma unroll
     for (int k = 0; k < 6; ++k) C[k * N + n] = k < 3 ? T(1) : T(0);
   }
 }
 
-// ---- moments rho_s, j_s from the stored populations --------------------------
+// ---- momenta j_s from the stored populations ------------------------------------
+// j_s = sum_i c_i f_i = sum_i c_i g_i (the rest parts w_i rho_s cancel).  The
+// densities are part of the encoding of the populations and stay as they are.
 template <typename T, typename S>
 __global__ void k_moments(AuxArgs<T, S> a) {
   const int r = blockIdx.y;
@@ -62,30 +64,23 @@ __global__ void k_moments(AuxArgs<T, S> a) {
   int64_t beg, end;
   node_range(R.n, beg, end);
   const S* f = a.P.f[par] + 38 * R.off;
-  T* rho = a.P.rho[par] + 2 * R.off;
   T* J = a.P.j[par] + 6 * R.off;
   for (int64_t n = beg + threadIdx.x; n < end; n += blockDim.x) {
-    T rs[2], js[2][3];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      const T sh = T(R.rho0[s]);
-      T rsum = 0, jx = 0, jy = 0, jz = 0;
+      T jx = 0, jy = 0, jz = 0;
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const T v = Store<T, S>::load(f + ((int64_t)s * Q + i) * N, n, wgt<T>(i) * sh);
-        rsum += v;
+      for (int i = 1; i < Q; ++i) {
+        const T v = Store<T, S>::load(f + ((int64_t)s * Q + i) * N, n);
         if (CX[i] != 0) jx += T(CX[i]) * v;
         if (CY[i] != 0) jy += T(CY[i]) * v;
         if (CZ[i] != 0) jz += T(CZ[i]) * v;
       }
-      rs[s] = rsum; js[s][0] = jx; js[s][1] = jy; js[s][2] = jz;
+      const T ikS = T(1.0 / Store<T, S>::kScale);
+      J[(3 * s) * N + n] = jx * ikS;
+      J[(3 * s + 1) * N + n] = jy * ikS;
+      J[(3 * s + 2) * N + n] = jz * ikS;
     }
-    rho[n] = rs[0];
-    rho[N + n] = rs[1];
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) J[(3 * s + d) * N + n] = js[s][d];
   }
 }
 

@@ -41,14 +41,13 @@ struct RunDev {
                               // (n padded so arrays do not alias in HBM channels)
   int64_t off;                // offset of this run inside the pools, in strides
   int32_t target;             // steps to take in the current step call
-  int32_t base;               // parity of the run's step count at call start
+  int32_t base;               // the run's step count at call start (mod 2^31)
   int32_t min_cc;             // smallest droplet piece counted (nodes)
   int32_t pad0;
   double u_wall, G;
   double tau[2], inv_tau[2];
   double inv_tauP, etaP_over_tauP, L2;
   double chi_lo, inv_chi_range;
-  double rho0[2];             // FP16S shift densities
 };
 
 // One tile of the step launch: a bx*by column block at (x0, y0) covering
@@ -58,8 +57,16 @@ struct Tile {
 };
 
 // ---- storage conversions -------------------------------------------------
-// Populations are stored as S and converted to the arithmetic type T; the
-// FP16 format stores the shifted value f - w_i rho0 (round to nearest even).
+// Populations are stored shifted: g_i = f_i - w_i rho_s(x), x the node that
+// holds the value and rho_s(x) the density array of the same parity (the
+// node's density).  Near equilibrium g_i is small, so rounding acts on the
+// deviation from equilibrium rather than on f itself: this is what lets
+// FP16 (11 significant bits) resolve both phases, and it cuts FP32/FP64
+// rounding of the stored state by the same factor.  Stored as S, in units of
+// 1/kScale (FP16 keeps g * 2^12, which moves the small deviations of the
+// minority phase out of the subnormal range; |g| < 1 stays far below the
+// FP16 maximum), arithmetic in T.  The time step rounds FP16 values
+// stochastically (put); set-up and import round to nearest even (store).
 template <typename T, typename S>
 struct Store;
 
@@ -69,35 +76,80 @@ struct Store;
 #define LBM_NT_STORES 1
 #endif
 
+// MurmurHash3's 32-bit finaliser (A. Appleby, public domain): a bijective
+// mixer, used as a counter-based generator.
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+// Marsaglia's xorshift32 step: further words from one hashed seed.
+__device__ __forceinline__ uint32_t xorshift32(uint32_t x) {
+  x ^= x << 13;
+  x ^= x >> 17;
+  x ^= x << 5;
+  return x;
+}
+
 template <typename T>
 struct Store<T, T> {
-  static __device__ __forceinline__ T load(const T* p, int64_t k, T /*shift*/) { return p[k]; }
-  static __device__ __forceinline__ void store(T* p, int64_t k, T v, T /*shift*/) {
+  static constexpr bool kRandom = false;
+  static constexpr double kScale = 1.0;
+  static __device__ __forceinline__ T load(const T* p, int64_t k) { return p[k]; }
+  // store v; returns the value as stored (r: random bits, unused here)
+  static __device__ __forceinline__ T put(T* p, int64_t k, T v, uint32_t /*r*/) {
 #if LBM_NT_STORES
     __builtin_nontemporal_store(v, p + k);
 #else
     p[k] = v;
 #endif
+    return v;
   }
-  static __device__ __forceinline__ T roundtrip(T v, T /*shift*/) { return v; }
+  static __device__ __forceinline__ void store(T* p, int64_t k, T v) { put(p, k, v, 0u); }
 };
+
+#ifndef LBM_FP16_RN
+#define LBM_FP16_RN 0   // 1: round to nearest even instead of stochastically
+#endif
 
 template <>
 struct Store<float, __half> {
-  static __device__ __forceinline__ float load(const __half* p, int64_t k, float shift) {
-    return __half2float(p[k]) + shift;
+  static constexpr bool kRandom = !LBM_FP16_RN;
+  static constexpr double kScale = 4096.0;
+  static __device__ __forceinline__ float load(const __half* p, int64_t k) {
+    return __half2float(p[k]);
   }
-  static __device__ __forceinline__ void store(__half* p, int64_t k, float v, float shift) {
+  static __device__ __forceinline__ void raw_store(__half* p, int64_t k, __half h) {
 #if LBM_NT_STORES
-    const __half h = __float2half_rn(v - shift);
     __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, h),
                                 reinterpret_cast<unsigned short*>(p) + k);
 #else
-    p[k] = __float2half_rn(v - shift);
+    p[k] = h;
 #endif
   }
-  static __device__ __forceinline__ float roundtrip(float v, float shift) {
-    return __half2float(__float2half_rn(v - shift)) + shift;
+  // Stochastic rounding to FP16 with 13 random bits r (bits 0..12): adding r
+  // to the 13 float mantissa bits that FP16 drops and then truncating them
+  // rounds |v| up with probability (|v| - lower)/spacing, so the rounding
+  // error has zero mean.  Deterministic rounding leaves the same error at
+  // every node of a uniform region, step after step, and that coherent bias
+  // accumulates in the flow.  The truncated value is an FP16 number in the
+  // normal range, so the final conversion is exact.
+  static __device__ __forceinline__ float put(__half* p, int64_t k, float v, uint32_t r) {
+#if LBM_FP16_RN
+    (void)r;
+    const __half h = __float2half_rn(v);
+#else
+    const uint32_t b = (__float_as_uint(v) + (r & 0x1fffu)) & 0xffffe000u;
+    const __half h = __float2half_rn(__uint_as_float(b));
+#endif
+    raw_store(p, k, h);
+    return __half2float(h);
+  }
+  static __device__ __forceinline__ void store(__half* p, int64_t k, float v) {
+    raw_store(p, k, __float2half_rn(v));
   }
 };
 

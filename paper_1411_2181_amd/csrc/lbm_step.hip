@@ -17,6 +17,8 @@
 //                 of the node's own outgoing population with the moving-wall
 //                 term -6 w_i rho_s c_i.u_wall.  The new density and momentum
 //                 of the component at x are summed from the values written.
+//                 Populations are held as g_i = f_i - w_i rho_s(node) (see
+//                 Store), and the collision is done in that variable.
 //   FENE-P pass   (per node, viscoelastic runs only): explicit Euler step of
 //                 C with u^n and C^n of the six face neighbours (first-order
 //                 upwind advection, centred grad u, Peterlin factor in FP64).
@@ -32,16 +34,25 @@
 
 namespace lbm {
 
+// Equilibrium minus its rest part, f^eq_i - w_i rho: the shifted equilibrium.
 template <typename T>
-__device__ __forceinline__ T feq(int i, T rho, T ux, T uy, T uz) {
+__device__ __forceinline__ T geq(int i, T rho, T ux, T uy, T uz) {
   const T cu = T(CX[i]) * ux + T(CY[i]) * uy + T(CZ[i]) * uz;
   const T usq = ux * ux + uy * uy + uz * uz;
-  return wgt<T>(i) * rho * (T(1) + T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
+  return wgt<T>(i) * rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
 }
 
 __device__ __forceinline__ int64_t nid(int x, int y, int z, int nx, int ny) {
   return ((int64_t)z * ny + y) * nx + x;
 }
+
+// Optional occupancy target of the collide pass (waves per SIMD), a build
+// option: the register budget then shrinks to 512 / waves.
+#ifdef LBM_COLLIDE_WAVES
+#define LBM_COLLIDE_OCC __attribute__((amdgpu_waves_per_eu(LBM_COLLIDE_WAVES)))
+#else
+#define LBM_COLLIDE_OCC
+#endif
 
 // Shapes of the tile (bx, by) with a compiled instance of every pass.
 #define LBM_FOR_SHAPES(M) M(64, 4) M(32, 8) M(128, 2) M(64, 2) M(32, 4)
@@ -206,7 +217,7 @@ __global__ void __launch_bounds__(BX * BY) k_force(StepArgs<T, S> a) {
 // ring, one barrier per plane): each record is read from HBM about once
 // instead of once by each of its 19 pulling neighbours.
 template <typename T, typename S, int BX, int BY>
-__global__ void __launch_bounds__(BX * BY) k_collide(StepArgs<T, S> a) {
+__global__ void __launch_bounds__(BX * BY) LBM_COLLIDE_OCC k_collide(StepArgs<T, S> a) {
   constexpr int HX = BX + 2, HY = BY + 2, HN = HX * HY, NT = BX * BY;
   __shared__ V4<T> ring[4][HN];
   const int g = *a.gstep;
@@ -231,7 +242,8 @@ __global__ void __launch_bounds__(BX * BY) k_collide(StepArgs<T, S> a) {
     const int ym = y == 0 ? ny - 1 : y - 1, yp = y >= ny - 1 ? 0 : y + 1;
     const T uw = T(R.u_wall);
     const T it = T(R.inv_tau[s]);
-    const T r0 = T(R.rho0[s]);
+    using St = Store<T, S>;
+    const T kS = T(St::kScale), ikS = T(1.0 / St::kScale);
     // copy plane zp of the tile + halo (periodic in x and y) into its slot;
     // positions beyond a ragged edge hold valid but unused nodes
     auto stage = [&](int zp) {
@@ -254,10 +266,9 @@ __global__ void __launch_bounds__(BX * BY) k_collide(StepArgs<T, S> a) {
         if (CZ[i] == 0 || (zs >= 0 && zs < nz)) {
           const int xs = CX[i] > 0 ? xm : (CX[i] < 0 ? xp : x);
           const int ys = CY[i] > 0 ? ym : (CY[i] < 0 ? yp : y);
-          v[i] = Store<T, S>::load(fs + (int64_t)i * N, nid(xs, ys, zs, nx, ny), wgt<T>(i) * r0);
+          v[i] = St::load(fs + (int64_t)i * N, nid(xs, ys, zs, nx, ny));
         } else {
-          const int o = OPPI[i];
-          v[i] = Store<T, S>::load(fs + (int64_t)o * N, m, wgt<T>(o) * r0);
+          v[i] = St::load(fs + (int64_t)OPPI[i] * N, m);
         }
       }
     };
@@ -277,31 +288,57 @@ __global__ void __launch_bounds__(BX * BY) k_collide(StepArgs<T, S> a) {
       if (active) {
         const int64_t n = nid(x, y, z, nx, ny);
         const int lc = (ty + 1) * HX + (tx + 1);
-        T rsum = 0, jx = 0, jy = 0, jz = 0;
+        // BGK collision of each arriving population in the shifted variable
+        // of the node that holds it (the record's node in both branches),
+        // g* = g - (g - g^eq)/tau, then re-referenced to the density rho_x of
+        // x: h_i = g*_i + w_i (rho_src,i - rho_x) = f*_i - w_i rho_x.  The new
+        // density is rho_x + sum_i h_i (sum_i w_i = 1): rho_x enters with
+        // weight exactly 1 and the rounded weights (FP32 sum 1 + 1.5e-8) only
+        // multiply small differences, so they do not leak into the mass.
+        // Shifted values are in storage units (times kScale, a power of 2).
+        const T rx = ring[z & 3][lc].x;
+        T drho = 0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          T fpost;
           const int zs = z - CZ[i];
           if (CZ[i] == 0 || (zs >= 0 && zs < nz)) {
             const V4<T> r = ring[zs & 3][lc - CY[i] * HX - CX[i]];
-            fpost = cur[i] - (cur[i] - feq<T>(i, r.x, r.y, r.z, r.w)) * it;
+            cur[i] = cur[i] - (cur[i] - geq<T>(i, r.x * kS, r.y, r.z, r.w)) * it;
+            if (i != 0) cur[i] += (wgt<T>(i) * kS) * (r.x - rx);
           } else {
             // half-way bounce-back: the population that left x in direction
-            // opp(i) is reflected by the wall it crossed
+            // opp(i) is reflected by the wall it crossed (source: x itself)
             const int o = OPPI[i];
             const V4<T> r = ring[z & 3][lc];
             const T uwall = CZ[o] > 0 ? uw : -uw;
-            fpost = cur[i] - (cur[i] - feq<T>(o, r.x, r.y, r.z, r.w)) * it
-                    - ((T(6) * wgt<T>(o)) * r.x) * (T(CX[o]) * uwall);
+            cur[i] = cur[i] - (cur[i] - geq<T>(o, r.x * kS, r.y, r.z, r.w)) * it
+                     - ((T(6) * kS * wgt<T>(o)) * r.x) * (T(CX[o]) * uwall);
           }
-          Store<T, S>::store(fo + (int64_t)i * N, n, fpost, wgt<T>(i) * r0);
-          // moments of the value as stored (FP16S re-reads its rounding)
-          const T fq = Store<T, S>::roundtrip(fpost, wgt<T>(i) * r0);
-          rsum += fq;
+          drho += cur[i];
+        }
+        const T rsum = rx + drho * ikS;
+        // stored: f*_i - w_i rho_x_new = h_i - w_i drho; the momentum is
+        // summed from the values as stored (the rest parts cancel pairwise
+        // in sum_i c_i w_i).  FP16 rounding draws 13 random bits per value
+        // from a hash of (node, component, step): independent of the tile
+        // shape and batch layout, and reproducible.
+        uint32_t rw = 0;
+        if (St::kRandom)
+          rw = fmix32((uint32_t)n * 0x9e3779b1u ^ fmix32((uint32_t)(R.base + g) * 2u + (uint32_t)s));
+        T jx = 0, jy = 0, jz = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          if (St::kRandom && i > 0 && (i & 1) == 0) rw = xorshift32(rw);
+          const uint32_t rb = (i & 1) ? (rw >> 16) : rw;
+          const T v = cur[i] - wgt<T>(i) * drho;
+          const T fq = St::put(fo + (int64_t)i * N, n, v, rb);
           if (CX[i] != 0) jx += T(CX[i]) * fq;
           if (CY[i] != 0) jy += T(CY[i]) * fq;
           if (CZ[i] != 0) jz += T(CZ[i]) * fq;
         }
+        jx *= ikS;
+        jy *= ikS;
+        jz *= ikS;
         rho_out[n] = rsum;
         j_out[n] = jx;
         j_out[N + n] = jy;

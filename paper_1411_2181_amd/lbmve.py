@@ -42,7 +42,6 @@ class LbmParams(ctypes.Structure):
         ("eta_P", ctypes.c_double * 2),
         ("L2", ctypes.c_double * 2),
         ("chi_lo", ctypes.c_double), ("chi_hi", ctypes.c_double),
-        ("rho0", ctypes.c_double * 2),
     ]
 
 
@@ -104,6 +103,12 @@ _SIGNATURES = {
     "lbm_batch_import": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.c_size_t]),
     "lbm_batch_nruns": (ctypes.c_int32, [ctypes.c_void_p]),
+    "lbm_batch_state_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm_batch_save_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.c_size_t]),
+    "lbm_batch_load_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.c_size_t]),
     "sg_param_count": (ctypes.c_int32, []),
     "sg_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "sg_init": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
@@ -164,8 +169,6 @@ def make_params(d: dict, precision: str = "fp64") -> LbmParams:
         arr[0], arr[1] = float(v[0]), float(v[1])
     p.chi_lo = float(d.get("chi_lo", 0.0))
     p.chi_hi = float(d.get("chi_hi", 0.0))
-    r0 = d.get("rho0", (0.0, 0.0))
-    p.rho0[0], p.rho0[1] = float(r0[0]), float(r0[1])
     return p
 
 
@@ -238,6 +241,19 @@ class Batch:
     def import_(self, field: str, values: np.ndarray, run: int = 0):
         v = np.ascontiguousarray(values, dtype=np.float64).ravel()
         _check(lib().lbm_batch_import(self._c(), run, FIELD[field], v.ctypes.data, v.size), f"import {field}")
+
+    def save_state(self, run: int = 0) -> bytes:
+        """Raw state of one run (populations as stored, densities, C, step
+        count) for a bit-exact restart."""
+        n = ctypes.c_size_t()
+        _check(lib().lbm_batch_state_bytes(self._c(), run, ctypes.byref(n)), "state_bytes")
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib().lbm_batch_save_state(self._c(), run, buf, n.value), "save_state")
+        return buf.raw
+
+    def load_state(self, blob: bytes, run: int = 0):
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        _check(lib().lbm_batch_load_state(self._c(), run, buf, len(blob)), "load_state")
 
     def step_profiled(self, nsteps: int):
         """Eager steps with HIP events around each pass; returns the summed

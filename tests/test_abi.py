@@ -108,6 +108,10 @@ def test_null_arguments_rejected(L):
     assert L.lbm_observe(None, 0, None) == lbmve.LBM_EINVAL
     assert L.lbm_export(None, 0, None, 0) == lbmve.LBM_EINVAL
     assert L.lbm_batch_nruns(None) == 0
+    n = ctypes.c_size_t()
+    assert L.lbm_batch_state_bytes(None, 0, ctypes.byref(n)) == lbmve.LBM_EINVAL
+    assert L.lbm_batch_save_state(None, 0, None, 0) == lbmve.LBM_EINVAL
+    assert L.lbm_batch_load_state(None, 0, None, 0) == lbmve.LBM_EINVAL
     p = lbmve.make_params(WL.small_newtonian())
     out = ctypes.c_void_p()
     # no workspace -> rejected before any device call
