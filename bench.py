@@ -4,20 +4,24 @@
 
 Workload: the matrix-viscoelastic droplet in confined shear on a 512x256x128
 lattice (W = 128), droplet R = 32 (2R/W = 0.5) at mid-gap, FENE-P in the
-matrix (L^2 = 400, De = 1, polymer fraction 0.4), viscosity ratio 0.5,
-Ca = 0.25; synthetic initial state (sphere at rest, C = I), inputs resident
-in HBM before the timed region.  One step = force pass + collide/stream/
-FENE-P pass over every node.  Prints ONE JSON line.
+matrix (L^2 = 400, De = 1, polymer fraction 0.4), viscosity ratio 0.5, wall
+speed 0.1 (Ca ~ 0.18; the work per update does not depend on Ca); synthetic
+initial state (sphere at rest, C = I), inputs resident in HBM before the
+timed region.  One step = force pass + collide/stream pass + FENE-P pass
+over every node.  Prints ONE JSON line.
 
-The launch shape is picked by the autotuner before the timed region.  The
-timed region replays the library's HIP graphs (the production path); the
-per-pass durations for the roofline come from HIP events around each pass
-in a second region of the same length on the same stream.
+The launch shape is picked by the autotuner before the timed region (or
+pinned with --launch).  The timed region replays the library's HIP graphs
+(the production path); the per-pass durations for the roofline come from HIP
+events around each pass in a second region of the same length on the same
+stream.  The roofline is given for the dominant kernel (collide-stream) and
+for the whole step; measured HBM traffic per dispatch comes from the
+committed rocprofv3 counter summary (profiles/traffic_mv512.json) while the
+kernel sources are unchanged.
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -31,6 +35,8 @@ METRIC = "MLUPS (D3Q19x2 + FENE-P), % HBM roofline; Ca_cr sweeps/hour at +/-0.01
 # algorithmic bytes per lattice update: read and write every population of
 # both components and every conformation component once
 B_ALG = {"fp64": 2 * (38 + 6) * 8, "fp32": 2 * (38 + 6) * 4, "fp16s": 2 * (38 * 2 + 6 * 4)}
+# the populations' share, moved by the collide-stream kernel
+B_ALG_COLLIDE = {"fp64": 2 * 38 * 8, "fp32": 2 * 38 * 4, "fp16s": 2 * 38 * 2}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f16 storage / f32 compute"}
 
 
@@ -56,19 +62,11 @@ def workload_params(nx=512, ny=256, nz=128, u_wall=0.1):
     return p, info
 
 
-def source_hash():
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1411_2181_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.startswith("lbm_"):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def measured_traffic(precision):
-    """HBM bytes per step from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources."""
+def measured_traffic(precision, launch):
+    """HBM bytes per dispatch of each step kernel at this launch shape, from
+    the committed rocprofv3 counter summary, if it was taken on the current
+    kernel sources (else None)."""
+    from paper_1411_2181_amd.build import source_hash
     path = os.path.join(ROOT, "profiles", "traffic_mv512.json")
     if not os.path.exists(path):
         return None
@@ -77,15 +75,21 @@ def measured_traffic(precision):
     entry = t.get(precision)
     if not entry or entry.get("source_hash") != source_hash():
         return None
-    return entry
+    return entry["launches"].get(f"{launch['bx']}x{launch['by']}x{launch['bz']}")
 
 
-def gpu_run(precision, steps, warmup, tune=True):
+def gpu_run(precision, steps, warmup, launch=None):
+    """Autotune (unless ``launch`` pins the shape), then the graph-replayed
+    timed region, then ``steps`` eager steps with HIP events per pass."""
     import torch
     from paper_1411_2181_amd import autotune, lbmve
     p, info = workload_params()
     s = lbmve.Solver(p, precision)
-    tuned = autotune.tune(s, steps=3, use_cache=False, save=False) if tune else None
+    if launch:
+        s.set_launch(**launch)
+        tuned = None
+    else:
+        tuned = autotune.tune(s, steps=3, use_cache=False, save=False)
     nodes = p["nx"] * p["ny"] * p["nz"]
     s.step(warmup)
     torch.cuda.synchronize()
@@ -145,6 +149,43 @@ def cpu_baseline(seconds=12.0):
                        f"({nodes} nodes, R=32), {n} steps after 1 warm-up step, {dt:.1f} s")
 
 
+def roofline(precision, r):
+    """Roofline of the dominant kernel (the collide-stream pass, about 60 % of
+    a step) and of the whole step, from the per-pass HIP-event durations."""
+    nodes = r["nodes"]
+    ms_force, ms_coll, ms_fene = r["ms"]
+    bc = B_ALG_COLLIDE[precision]
+    ach = bc * nodes / (ms_coll * 1e-3) / 1e9
+    step_ms = ms_force + ms_coll + ms_fene
+    balg = B_ALG[precision]
+    step_ach = balg * nodes / (step_ms * 1e-3) / 1e9
+    tr = measured_traffic(precision, r["launch"])
+    step = {
+        "kernels": "k_force + k_collide + k_fene",
+        "bytes_alg_per_update": balg,
+        "achieved": round(step_ach, 1),
+        "frac": round(step_ach / HBM_PEAK_GBS, 4),
+        "ms_per_pass": {"force": round(ms_force, 4), "collide": round(ms_coll, 4),
+                        "fene": round(ms_fene, 4)},
+        "traffic_per_update": tr["step_bytes_per_node"] if tr else None,
+    }
+    if tr:
+        moved = tr["step_bytes_per_node"] * nodes
+        step["achieved_actual"] = round(moved / (step_ms * 1e-3) / 1e9, 1)
+    return {
+        "bound": "hbm",
+        "kernel": "k_collide (collide, stream and bounce-back; both components)",
+        "achieved": round(ach, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(ach / HBM_PEAK_GBS, 4),
+        "traffic": tr["k_collide"]["bytes"] if tr else None,
+        "bytes_alg_per_node": bc,
+        "ms_per_launch": round(ms_coll, 4),
+        "step": step,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,7 +196,13 @@ def main():
     ap.add_argument("--variants", default="fp16s", help="extra storage precisions to report")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="short run for rocprofv3 counter collection (prints no JSON)")
+    ap.add_argument("--launch", default="",
+                    help="pin the launch shape BXxBYxBZ instead of autotuning (profiling runs)")
     args = ap.parse_args()
+    launch = None
+    if args.launch:
+        bx, by, bz = (int(v) for v in args.launch.lower().split("x"))
+        launch = dict(bx=bx, by=by, bz=bz, persistent=0)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; "
                                    "multi-GPU slab decomposition is a design note"}))
@@ -166,13 +213,9 @@ def main():
         pmc_pass(args.precision)
         return
 
-    r = gpu_run(args.precision, args.steps, args.warmup)
+    r = gpu_run(args.precision, args.steps, args.warmup, launch)
     nodes, wall = r["nodes"], r["wall"]
     mlups = nodes * args.steps / wall / 1e6
-    step_ms = sum(r["ms"])
-    balg = B_ALG[args.precision]
-    achieved = balg * nodes / (step_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.precision)
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -197,29 +240,15 @@ def main():
             "tau_P": round(r["params"]["tau_P"][1], 2),
             "launch": r["launch"],
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "one step = k_force + k_collide + k_fene",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic["bytes_per_step"] if traffic else None,
-            "bytes_alg_per_update": balg,
-            "ms_per_pass": {"force": round(r["ms"][0], 4), "collide": round(r["ms"][1], 4),
-                            "fene": round(r["ms"][2], 4)},
-        },
+        "roofline": roofline(args.precision, r),
     }
     variants = [v for v in args.variants.split(",") if v and v != args.precision]
     for v in variants:
         rv = gpu_run(v, args.steps, args.warmup)
         mv = rv["nodes"] * args.steps / rv["wall"] / 1e6
-        sm = sum(rv["ms"])
-        ach = B_ALG[v] * rv["nodes"] / (sm * 1e-3) / 1e9
         out[f"variant_{v}"] = {"value": round(mv, 1), "unit": "MLUPS",
-                               "achieved_GBs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
-                               "bytes_alg_per_update": B_ALG[v], "launch": rv["launch"],
-                               "ms_per_pass": [round(m, 4) for m in rv["ms"]]}
+                               "ms_per_step": round(rv["wall"] / args.steps * 1e3, 4),
+                               "launch": rv["launch"], "roofline": roofline(v, rv)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

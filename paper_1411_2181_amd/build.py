@@ -61,6 +61,18 @@ def build(verbose: bool = False, out: str = OUT, defines=()) -> str:
     return OUTP
 
 
+def source_hash() -> str:
+    """Hash of the step-kernel sources (csrc/lbm_*): measurements taken on
+    other sources are not reported as current."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.startswith("lbm_"):
+            with open(os.path.join(CSRC, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def clean() -> None:
     shutil.rmtree(BUILD, ignore_errors=True)
 

@@ -1,0 +1,166 @@
+"""Summaries of rocprofv3 output for the step kernels.
+
+    python -m paper_1411_2181_amd.profsum trace KERNEL_TRACE.csv [--box 512,256,128]
+    python -m paper_1411_2181_amd.profsum traffic FETCH.csv WRITE.csv --precision fp32 \
+        [--json profiles/traffic_mv512.json] [--box 512,256,128]
+
+``trace`` groups the dispatches of a ``--kernel-trace`` run by kernel and
+launch shape (bx x by x bz, recovered from the grid size and the box) and
+prints their mean durations as a Markdown table.
+
+``traffic`` turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of
+``bench.py --pmc-pass`` into HBM bytes per dispatch.  Each counter is scaled
+by what it reads for the pass's reference copy (a 1 GiB device-to-device
+copy: 1 GiB read, 1 GiB written), which absorbs the counters' units (on
+gfx950 FETCH_SIZE reads about half the bytes a copy moves).  The per-launch
+table is merged into a JSON file together with the hash of the kernel sources
+it was taken on; bench.py only reports it while the sources are unchanged.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import json
+import os
+import re
+import statistics
+from collections import defaultdict
+
+from .build import source_hash
+
+COPY_BYTES = 1 << 30
+_STEP = re.compile(r"lbm::k_(force|collide|fene)<[^,]+, [^,]+, (\d+), (\d+)>")
+
+
+def _launch(kind, bx, by, grid_items, wg_items, box):
+    nx, ny, nz = box
+    wg = grid_items // wg_items
+    if kind == "collide":
+        wg //= 2                      # one workgroup per component
+    cols = -(-nx // bx) * -(-ny // by)
+    bz = nz * cols // wg if wg else 0
+    return f"{bx}x{by}x{bz}"
+
+
+def step_dispatches(path, box):
+    """(kernel, launch, duration_ns, counter_value or None) per step dispatch."""
+    out = []
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            m = _STEP.search(r["Kernel_Name"])
+            if not m:
+                continue
+            kind, bx, by = m.group(1), int(m.group(2)), int(m.group(3))
+            if "Grid_Size" in r:           # counter-collection rows: totals
+                grid, wg_items = int(r["Grid_Size"]), int(r["Workgroup_Size"])
+            else:                          # kernel-trace rows: per dimension
+                grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+                wg_items = (int(r["Workgroup_Size_X"]) * int(r["Workgroup_Size_Y"]) *
+                            int(r["Workgroup_Size_Z"]))
+            key = _launch(kind, bx, by, grid, wg_items, box)
+            dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            val = float(r["Counter_Value"]) if "Counter_Value" in r else None
+            out.append((kind, key, dur, val))
+    return out
+
+
+def copy_reference(path):
+    """Counter value of the pass's 1 GiB reference copy (largest copy dispatch)."""
+    best = None
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            if "copyBuffer" in r["Kernel_Name"] or "copy" in r["Kernel_Name"].lower():
+                v = float(r["Counter_Value"])
+                if best is None or int(r["Grid_Size"]) > best[0]:
+                    best = (int(r["Grid_Size"]), v)
+    if best is None:
+        raise ValueError(f"no copy dispatch in {path}")
+    return best[1]
+
+
+def trace_table(path, box, tail=0):
+    """Mean durations per (kernel, launch); ``tail`` > 0 keeps only the last
+    ``tail`` dispatches of each (bench.py ends with that many eager steps
+    timed by HIP events, after the graph-replayed region)."""
+    groups = defaultdict(list)
+    for kind, key, dur, _ in step_dispatches(path, box):
+        groups[(kind, key)].append(dur)
+    rows = []
+    for (kind, key), d in groups.items():
+        if tail > 0:
+            d = d[-tail:]
+        rows.append(dict(kernel=f"k_{kind}", launch=key, calls=len(d), mean_us=statistics.mean(d) / 1e3,
+                         min_us=min(d) / 1e3, max_us=max(d) / 1e3, total_ms=sum(d) / 1e6))
+    rows.sort(key=lambda r: -r["total_ms"])
+    return rows
+
+
+def traffic_table(fetch_csv, write_csv, box):
+    """{launch: {kernel: {"fetch": B, "write": B, "bytes": B, "us": mean}}} per dispatch."""
+    nodes = box[0] * box[1] * box[2]
+    scale = {"fetch": COPY_BYTES / (copy_reference(fetch_csv) * 1024.0),
+             "write": COPY_BYTES / (copy_reference(write_csv) * 1024.0)}
+    acc = defaultdict(lambda: defaultdict(lambda: defaultdict(list)))
+    for which, path in (("fetch", fetch_csv), ("write", write_csv)):
+        for kind, key, dur, val in step_dispatches(path, box):
+            acc[key][f"k_{kind}"][which].append(val * 1024.0 * scale[which])
+            acc[key][f"k_{kind}"]["us"].append(dur / 1e3)
+    table = {}
+    for key, ks in acc.items():
+        ent = {}
+        for k, v in ks.items():
+            if not v["fetch"] or not v["write"]:
+                continue
+            f, w = statistics.mean(v["fetch"]), statistics.mean(v["write"])
+            ent[k] = dict(fetch=round(f), write=round(w), bytes=round(f + w),
+                          bytes_per_node=round((f + w) / nodes, 2), us=round(statistics.mean(v["us"]), 1))
+        if len(ent) == 3:
+            ent["step_bytes_per_node"] = round(sum(e["bytes"] for e in ent.values()) / nodes, 2)
+            table[key] = ent
+    return table, scale
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("csv")
+    t.add_argument("--box", default="512,256,128")
+    t.add_argument("--tail", type=int, default=0)
+    p = sub.add_parser("traffic")
+    p.add_argument("fetch_csv")
+    p.add_argument("write_csv")
+    p.add_argument("--precision", required=True)
+    p.add_argument("--json")
+    p.add_argument("--box", default="512,256,128")
+    a = ap.parse_args(argv)
+    box = tuple(int(v) for v in a.box.split(","))
+    if a.cmd == "trace":
+        print("| kernel | launch (bx x by x bz) | calls | mean us | min us | max us |")
+        print("|---|---|---|---|---|---|")
+        for r in trace_table(a.csv, box, a.tail):
+            print(f"| {r['kernel']} | {r['launch']} | {r['calls']} | {r['mean_us']:.1f} | "
+                  f"{r['min_us']:.1f} | {r['max_us']:.1f} |")
+        return 0
+    table, scale = traffic_table(a.fetch_csv, a.write_csv, box)
+    print(f"copy-reference scale factors: FETCH_SIZE x{scale['fetch']:.4f}, WRITE_SIZE x{scale['write']:.4f}")
+    print("| launch | k_force B/node | k_collide B/node | k_fene B/node | step B/node |")
+    print("|---|---|---|---|---|")
+    for key in sorted(table, key=lambda k: table[k]["step_bytes_per_node"]):
+        e = table[key]
+        print(f"| {key} | {e['k_force']['bytes_per_node']} | {e['k_collide']['bytes_per_node']} | "
+              f"{e['k_fene']['bytes_per_node']} | {e['step_bytes_per_node']} |")
+    if a.json:
+        data = {}
+        if os.path.exists(a.json):
+            with open(a.json) as fh:
+                data = json.load(fh)
+        data[a.precision] = dict(source_hash=source_hash(), box=list(box),
+                                 scale=scale, launches=table)
+        with open(a.json, "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
