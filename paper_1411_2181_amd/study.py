@@ -1,24 +1,33 @@
-"""Surrogate study: generate runs with the batched solver, train the network
-on them, and compare surrogate-bracketed Ca_cr searches with plain
-bisection on the same GPU.
+"""Surrogate study: runs from the batched solver train the network, which
+then proposes Ca_cr brackets; plain bisection on the same GPU is the
+reference.
 
-    python -m paper_1411_2181_amd.study OUT.json [--runs 600] [--queries 32]
+    python -m paper_1411_2181_amd.study generate DATA.json [--runs 160] [--skip 0]
+    python -m paper_1411_2181_amd.study search OUT.json --data DATA.json[,DATA2.json] \
+        [--queries 16] [--fp64-queries 1]
 
-Workload readings (the reachable-parameter window of the lattice model):
-R ~ U[12, 16] (break-up within the reachable Ca needs R >~ 16: the Reynolds
-number at the wall-speed cap grows with R), lambda from {0.5, 0.75} (a droplet
-tau of 1.5 or more dissolves the droplet at this coupling; lambda 1 and 2 are
-outside the window), confinement c in {0.3, 0.5, 0.7}, De in {0, 0.5, 1, 2},
-L^2 in {100, 400}, polymer fraction in {0.2, 0.4}; Ca ~ U[0.03, Ca_max],
-Ca_max the value at the U_w = 0.19 wall-speed cap.  Each run lasts 8000 steps
-(break-up, when it happens, does so by ~8000 steps) and is checked for
-break-up every 1000 steps.  Query triples use R = 16.
+Study window (the part of parameter space where the droplet breaks at a
+reachable capillary number): R = 24 (Reynolds number 5-7 at the wall-speed
+cap, where break-up sets in at Ca ~ 0.2), confinement c ~ U[0.45, 0.6],
+viscosity ratio lambda ~ U[0.6, 0.9] (below ~0.6 a viscoelastic droplet's
+solvent tau drops under ~0.85 and runs at the wall-speed cap lose
+stability), De in {0, 0.5, 1, 2}, L^2 in {100, 400}, polymer fraction in
+{0.2, 0.4}, droplet viscoelastic.  Ca ~ U[CA_LO, Ca_max], Ca_max the value at
+the U_w = 0.19 cap.  Each run lasts up to T_END steps and is checked for
+break-up every EVERY steps (a run stops once it breaks).
+
+Searches: tolerance 0.02 (Ca_cr located within +-0.01), window
+[CA_LO, Ca_max] with CA_LO taken as stable.  Plain bisection starts from the
+window; the surrogate's search starts from a bracket of width 0.02 around
+the Ca where its break-up logit crosses zero and falls back outward when a
+bracket end fails (sweep.bisect).  Both advance every query's runs of a round
+as one batch (FP32).  The plain FP64 one-run-at-a-time variant is timed on
+``--fp64-queries`` triples.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import sys
 import time
 
@@ -29,61 +38,94 @@ import workloads as WL
 from . import sweep
 from .surrogate import Surrogate
 
+CA_LO = 0.10
+T_END = 16000
+EVERY = 2000
+TOL = 0.02
+
 
 def sample_specs(n: int, base_seed: int = 98765):
     specs = []
     for k in range(n):
-        d = WL.surrogate_sampler(k, base_seed)
-        rng = np.random.default_rng(d["seed"] + 17)
-        R = float(rng.uniform(12.0, 16.0))
-        lam = 0.5 if d["lam"] <= 0.5 else 0.75
-        hi = sweep.ca_max(R, d["confinement"], lam, d["De"], d["polymer_fraction"])
-        Ca = float(rng.uniform(0.03, hi))
-        specs.append(sweep.RunSpec(R, d["confinement"], Ca, d["De"], lam, d["L2"],
+        d = WL.surrogate_window_sampler(k, base_seed)
+        hi = sweep.ca_max(d["R"], d["confinement"], d["lam"], d["De"], d["polymer_fraction"])
+        Ca = CA_LO + d["u"] * (hi - CA_LO)
+        specs.append(sweep.RunSpec(d["R"], d["confinement"], Ca, d["De"], d["lam"], d["L2"],
                                    d["polymer_fraction"]))
     return specs
 
 
-def generate(specs, chunk: int = 80, steps: int = 8000, log=print):
+def generate(specs, chunk: int = 20, log=print, save=None):
     rows, secs, updates = [], 0.0, 0
     for i in range(0, len(specs), chunk):
         part = specs[i:i + chunk]
-        res, sec = sweep.simulate(part, "fp32", t_end=steps, every=1000)
+        res, sec = sweep.simulate(part, "fp32", t_end=T_END, every=EVERY, progress=log)
         secs += sec
         for r in res:
             n = r.params["nx"] * r.params["ny"] * r.params["nz"]
             updates += n * r.steps
             rows.append(dict(inputs=r.spec.inputs(), D=r.D, theta=r.theta, broken=bool(r.broken),
-                             status=r.status, steps=r.steps, Lp_max=r.Lp_max))
+                             step_break=r.step_break, status=r.status, steps=r.steps,
+                             Lp_max=r.Lp_max, R=r.spec.R))
         log(f"generated {i + len(part)}/{len(specs)} runs, {secs:.1f} s, "
-            f"{updates / secs / 1e6:.0f} MLUPS (batched FP32)")
+            f"{updates / secs / 1e6:.0f} MLUPS (batched FP32), "
+            f"{sum(r['broken'] for r in rows)} broken")
+        if save:
+            save(rows, secs, updates)
     return rows, secs, updates
 
 
-def query_searches(n: int, R: float = 16.0):
-    out = []
-    for q in WL.query_triples(n):
-        lam = min(max(q["lam"], 0.5), 0.8)
-        out.append(dict(De=q["De"], lam=lam, c=q["confinement"], R=R))
-    return out
+def query_searches(n: int):
+    return [dict(De=q["De"], lam=q["lam"], c=q["confinement"], R=q["R"]) for q in WL.query_window(n)]
 
 
-def main(argv=None):
-    ap = argparse.ArgumentParser()
-    ap.add_argument("out")
-    ap.add_argument("--runs", type=int, default=320)
-    ap.add_argument("--queries", type=int, default=32)
-    ap.add_argument("--epochs", type=int, default=3000)
-    args = ap.parse_args(argv)
-    log = lambda s: print(s, flush=True)
-    report = {}
+def window(q):
+    return CA_LO, sweep.ca_max(q["R"], q["c"], q["lam"], q["De"])
 
-    # 1. training data from the solver itself
-    specs = sample_specs(args.runs)
-    rows, sec, upd = generate(specs, log=log)
+
+def single_runner(precision: str, log=None):
+    """One run at a time (no batching): the plain reference path."""
+    def run(specs):
+        out, total = [], 0.0
+        for sp in specs:
+            res, sec = sweep.simulate([sp], precision, t_end=T_END, every=EVERY, progress=log)
+            total += sec
+            out.append((res[0].broken, res[0].status))
+        return out, total
+    return run
+
+
+def cmd_generate(args, log):
+    specs = sample_specs(args.runs + args.skip)[args.skip:]
+
+    def save(rows, sec, upd):
+        with open(args.out, "w") as fh:
+            json.dump(dict(window=dict(R=24.0, ca_lo=CA_LO, t_end=T_END, every=EVERY),
+                           first_run=args.skip, seconds=sec, updates=upd, rows=rows), fh, indent=1)
+
+    generate(specs, log=log, save=save)
+    return 0
+
+
+def load_data(paths):
+    """Merge generate outputs (each a slice of the same sampler sequence)."""
+    rows, sec, upd = [], 0.0, 0
+    for p in paths:
+        with open(p) as fh:
+            d = json.load(fh)
+        rows += d["rows"]
+        sec += d["seconds"]
+        upd += d["updates"]
+    return dict(rows=rows, seconds=sec, updates=upd)
+
+
+def cmd_search(args, log):
+    data = load_data(args.data.split(","))
+    rows = data["rows"]
     ok = [r for r in rows if r["status"] == 0]
-    report["data"] = dict(runs=len(rows), usable=len(ok), broken=sum(r["broken"] for r in ok),
-                          seconds=sec, updates=upd, mlups=upd / sec / 1e6)
+    report = dict(data=dict(runs=len(rows), usable=len(ok), broken=sum(r["broken"] for r in ok),
+                            failed=len(rows) - len(ok), seconds=data["seconds"],
+                            mlups=data["updates"] / data["seconds"] / 1e6))
     X = np.array([r["inputs"] for r in ok])
     D = np.array([r["D"] for r in ok])
     TH = np.array([r["theta"] for r in ok])
@@ -93,8 +135,8 @@ def main(argv=None):
     nte = max(1, len(ok) // 10)
     te, tr = perm[:nte], perm[nte:]
 
-    # 2. train on the GPU with the project's kernels
-    sg = Surrogate(batch_max=max(4096, len(tr)), seed=1)
+    # train on the GPU with the project's kernels
+    sg = Surrogate(batch_max=max(4096, len(ok)), seed=1)
     t0 = time.perf_counter()
     losses = sg.fit(X[tr], D[tr], TH[tr], BR[tr], epochs=args.epochs, lr=2e-3)
     report["train"] = dict(rows=int(tr.size), epochs=args.epochs, loss_first=losses[0],
@@ -102,61 +144,101 @@ def main(argv=None):
     pD, pT, pB = sg.predict(X[te])
     unb = BR[te] < 0.5
     report["holdout"] = dict(
-        rows=int(te.size),
+        rows=int(te.size), broken=int(BR[te].sum()),
         mae_D=float(np.mean(np.abs(pD[unb] - D[te][unb]))) if unb.any() else None,
         mae_theta_deg=float(np.mean(np.abs(pT[unb] - TH[te][unb]))) if unb.any() else None,
         breakup_accuracy=float(np.mean((pB >= 0.5) == (BR[te] > 0.5))))
     log(json.dumps(report))
+    # refit on every usable row for the searches
+    sg.close()
+    sg = Surrogate(batch_max=max(4096, len(ok)), seed=1)
+    sg.fit(X, D, TH, BR, epochs=args.epochs, lr=2e-3)
 
-    # 3. Ca_cr searches: plain bisection vs surrogate-proposed brackets
     qs = query_searches(args.queries)
-    plain = [sweep.Search(q["De"], q["lam"], q["c"], q["R"], 0.0, 1e9) for q in qs]
-    plain, t_plain, r_plain = sweep.bisect(plain, tol=0.02, verify_ends=False, t_end=8000)
+
+    def plain_searches():
+        out = []
+        for q in qs:
+            lo, hi = window(q)
+            out.append(sweep.Search(q["De"], q["lam"], q["c"], q["R"], lo, hi, hard_lo=lo, hard_hi=hi))
+        return out
+
+    # plain bisection, batched FP32
+    plain, t_plain, r_plain = sweep.bisect(plain_searches(), tol=TOL,
+                                           run=sweep.lattice_runner("fp32", log=log, t_end=T_END, every=EVERY))
     log(f"plain bisection: {t_plain:.1f} s, {r_plain} rounds, {sum(s.runs for s in plain)} runs")
-    prop = []
+
+    # surrogate-proposed brackets, batched FP32
+    prop, proposals = [], []
     for q in qs:
-        hi = sweep.ca_max(q["R"], q["c"], q["lam"], q["De"])
-        b = sg.propose(q["De"], q["lam"], q["c"], 0.02, hi)
-        lo_b, hi_b = b if b is not None else (0.02, hi)
-        prop.append(sweep.Search(q["De"], q["lam"], q["c"], q["R"], lo_b, hi_b))
-    prop, t_sg, r_sg = sweep.bisect(prop, tol=0.02, verify_ends=True, t_end=8000)
+        lo, hi = window(q)
+        b = sg.propose(q["De"], q["lam"], q["c"], lo, hi, margin=TOL / 2)
+        proposals.append(b)
+        blo, bhi = b if b is not None else (lo, hi)
+        prop.append(sweep.Search(q["De"], q["lam"], q["c"], q["R"], blo, bhi, hard_lo=lo, hard_hi=hi))
+    prop, t_sg, r_sg = sweep.bisect(prop, tol=TOL,
+                                    run=sweep.lattice_runner("fp32", log=log, t_end=T_END, every=EVERY))
     log(f"surrogate-bracketed: {t_sg:.1f} s, {r_sg} rounds, {sum(s.runs for s in prop)} runs")
-    rows_q = []
-    agree = 0
-    comparable = 0
-    for q, a, b in zip(qs, plain, prop):
-        rq = dict(q, plain=a.ca_cr, plain_outside=a.outside, surrogate=b.ca_cr,
-                  surrogate_outside=b.outside, runs_plain=a.runs, runs_surrogate=b.runs)
-        if not b.outside and a.lo > a.hard_lo + 1e-9 and a.hi < a.hard_hi - 1e-9:
+
+    rows_q, agree, comparable = [], 0, 0
+    for q, a, b, pb in zip(qs, plain, prop, proposals):
+        rows_q.append(dict(q, window=list(window(q)), proposal=pb,
+                           plain=dict(ca_cr=a.ca_cr, bracket=[a.lo, a.hi], outside=a.outside,
+                                      runs=a.runs, rounds=a.rounds),
+                           surrogate=dict(ca_cr=b.ca_cr, bracket=[b.lo, b.hi], outside=b.outside,
+                                          runs=b.runs, rounds=b.rounds)))
+        if a.outside == b.outside:
             comparable += 1
-            agree += abs(a.ca_cr - b.ca_cr) <= 0.02
-        rows_q.append(rq)
+            agree += (a.outside != "" or abs(a.ca_cr - b.ca_cr) <= TOL)
     report["search"] = dict(
-        queries=len(qs), tol=0.02,
+        queries=len(qs), tol=TOL, t_end=T_END,
         plain=dict(seconds=t_plain, rounds=r_plain, runs=sum(s.runs for s in plain),
                    sweeps_per_hour=len(qs) / t_plain * 3600),
         surrogate=dict(seconds=t_sg, rounds=r_sg, runs=sum(s.runs for s in prop),
                        sweeps_per_hour=len(qs) / t_sg * 3600,
-                       verified_first_try=sum(1 for s in prop if s.runs <= 3)),
-        comparable=comparable, agree_within_0p02=agree, rows=rows_q)
+                       first_round_hits=sum(1 for s in prop if s.rounds == 1 and s.outside == "")),
+        same_outcome=comparable, agree_within_tol=agree, rows=rows_q)
 
-    # 4. plain FP64 one-run-at-a-time bisection on two triples (extrapolated)
-    t64 = 0.0
-    n64 = 0
-    for q in qs[:2]:
-        s = [sweep.Search(q["De"], q["lam"], q["c"], q["R"], 0.0, 1e9)]
-        _, t, _ = sweep.bisect(s, tol=0.02, verify_ends=False, precision="fp64", t_end=8000)
+    # plain FP64, one run at a time, on the first triples
+    t64, n64, runs64 = 0.0, 0, 0
+    for q in qs[:args.fp64_queries]:
+        lo, hi = window(q)
+        s64 = [sweep.Search(q["De"], q["lam"], q["c"], q["R"], lo, hi, hard_lo=lo, hard_hi=hi)]
+        s64, t, _ = sweep.bisect(s64, tol=TOL, run=single_runner("fp64", log))
         t64 += t
         n64 += 1
-    report["search"]["plain_fp64_single"] = dict(
-        triples_timed=n64, seconds=t64, sweeps_per_hour=n64 / t64 * 3600)
+        runs64 += s64[0].runs
+        log(f"fp64 single: query {n64} {t:.1f} s, {s64[0].runs} runs, Ca_cr {s64[0].ca_cr:.3f} "
+            f"({s64[0].outside or 'inside'}); batched plain {plain[n64 - 1].ca_cr:.3f}")
+    if n64:
+        report["search"]["plain_fp64_single"] = dict(triples_timed=n64, seconds=t64, runs=runs64,
+                                                     sweeps_per_hour=n64 / t64 * 3600)
     sg.close()
     with open(args.out, "w") as fh:
         json.dump(report, fh, indent=1)
-    log(json.dumps(report["search"]["plain"]))
-    log(json.dumps(report["search"]["surrogate"]))
-    log(json.dumps(report["search"]["plain_fp64_single"]))
+    for k in ("plain", "surrogate", "plain_fp64_single"):
+        if k in report["search"]:
+            log(k + " " + json.dumps(report["search"][k]))
+    log(f"same outcome {comparable}/{len(qs)}, agree within tol {agree}")
     return 0
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    g = sub.add_parser("generate")
+    g.add_argument("out")
+    g.add_argument("--runs", type=int, default=160)
+    g.add_argument("--skip", type=int, default=0, help="start at this run of the sampler sequence")
+    s = sub.add_parser("search")
+    s.add_argument("out")
+    s.add_argument("--data", required=True, help="comma-separated generate outputs")
+    s.add_argument("--queries", type=int, default=16)
+    s.add_argument("--epochs", type=int, default=3000)
+    s.add_argument("--fp64-queries", type=int, default=1)
+    args = ap.parse_args(argv)
+    log = lambda m: print(m, flush=True)
+    return cmd_generate(args, log) if args.cmd == "generate" else cmd_search(args, log)
 
 
 if __name__ == "__main__":

@@ -4,9 +4,9 @@ The network (include/lbmve_surrogate.h; kernels in csrc/sg_kernels.hip)
 maps the six run parameters (Ca, De, lambda, 2R/W, L^2, polymer fraction)
 to (steady D, orientation / 45 degrees, break-up logit).  It is trained on
 runs the solver itself produced, and only *proposes* where to bracket the
-critical capillary number: every proposed bracket is verified by full
-simulations (sweep.bisect with verify_ends=True), and a bracket that fails
-verification falls back to plain bisection.
+critical capillary number: both ends of a proposed bracket are verified by
+full simulations (sweep.bisect), and a bracket end that fails moves the
+search outward until simulations confirm a bracket.
 """
 from __future__ import annotations
 

@@ -3,15 +3,16 @@
 The paper locates Ca_cr for each (De, lambda, 2R/W) by finding the largest
 wall speed at which the droplet is stable and the smallest at which it
 breaks (Section 3, set-up paragraph).  Here each search is a bisection in Ca
-whose runs are advanced together in one batched context (every round of
-every query triple in one launch sequence); break-up is a droplet split into
-two or more pieces of at least 1 % of its volume (6-connected components).
+whose runs are advanced together in one batched context (every query's runs
+of a round in one launch sequence); break-up is a droplet split into two or
+more pieces of at least 1 % of its volume (6-connected components).
 
 Lattice mapping (physics.lattice_params): Shan-Chen G = 0.75, matrix solvent
-tau = 1.5 (the top of the calibrated window), U_w <= 0.19; the box is (16R) x (3R) x (2R/c): long enough in
-the flow direction that an elongated droplet breaks instead of joining its
-periodic image.  The reachable Ca range depends on (c, lambda) through the
-wall-speed cap and is reported with every search.
+tau = 1.5 (the top of the calibrated window), U_w <= 0.19; the box is
+(16R) x (3R) x (2R/c): long enough in the flow direction that an elongated
+droplet breaks instead of joining its periodic image.  Ca_max, the Ca at the
+wall-speed cap, is eta_M c U_max / sigma: it does not depend on R, and it
+bounds every search window.
 """
 from __future__ import annotations
 
@@ -88,11 +89,13 @@ def lattice(spec: RunSpec):
 
 
 def simulate(specs, precision: str = "fp32", t_end: int | None = None, every: int = 1000,
-             min_steps: int = 4000, max_steps: int = 40000, device="cuda:0", launch=None):
+             min_steps: int = 4000, max_steps: int = 40000, device="cuda:0", launch=None,
+             progress=None):
     """Advance every run (one batch) to its end time, checking for break-up
     every ``every`` steps; a broken run is stopped (masked) at once.  Steady
     D and orientation are averaged over the last three checks of unbroken
-    runs.  Returns (results, seconds)."""
+    runs; ``progress`` (a callable) receives a line after every check.
+    Returns (results, seconds)."""
     results, runs = [], []
     for sp in specs:
         p, info = lattice(sp)
@@ -127,6 +130,10 @@ def simulate(specs, precision: str = "fp32", t_end: int | None = None, every: in
                 r.broken = True
                 r.step_break = o["step"]
                 remaining[k] = 0
+        if progress:
+            progress(f"  step {max(r.steps for r in results)}: "
+                     f"{sum(1 for v in remaining if v > 0)} running, "
+                     f"{sum(r.broken for r in results)} broken, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     b.close()
     for r in results:
@@ -139,83 +146,120 @@ def simulate(specs, precision: str = "fp32", t_end: int | None = None, every: in
 
 @dataclass
 class Search:
+    """One Ca_cr search: the bracket [lo, hi] (lo stable, hi broken once
+    verified) inside the hard window [hard_lo, hard_hi]."""
     De: float
     lam: float
     c: float
     R: float
     lo: float
     hi: float
-    lo_ok: bool = False      # lo verified stable
+    hard_lo: float = 0.0
+    hard_hi: float = 0.0
+    lo_ok: bool = False      # lo verified (or assumed) stable
     hi_ok: bool = False      # hi verified broken
     runs: int = 0
+    rounds: int = 0
     done: bool = False
-    outside: str = ""        # "below" / "above" when Ca_cr is outside the range
+    outside: str = ""        # "below" / "above" (Ca_cr outside the window) or "failed"
 
     @property
     def ca_cr(self):
         return 0.5 * (self.lo + self.hi)
 
 
-def bisect(searches, tol: float = 0.02, precision: str = "fp32", verify_ends: bool = True,
-           max_rounds: int = 12, **sim_kw):
-    """Bisection in Ca for every search at once.  If ``verify_ends``, the
-    first round simulates both bracket ends (a proposed bracket must be
-    confirmed: lo stable, hi broken); a failed end widens the bracket toward
-    the hard limits [0.02, Ca_max].  Returns (searches, seconds, rounds)."""
-    total = 0.0
-    rounds = 0
+def lattice_runner(precision: str = "fp32", log=None, **sim_kw):
+    """Default run function of bisect: full simulations, one batch per round.
+    Returns ([(broken, status)], seconds)."""
+    def run(specs):
+        if log:
+            log(f" round of {len(specs)} runs")
+        res, sec = simulate(specs, precision, progress=log, **sim_kw)
+        return [(r.broken, r.status) for r in res], sec
+    return run
+
+
+def bisect(searches, tol: float = 0.02, run=None, max_rounds: int = 12):
+    """Bisection in Ca for every search at once (each round's runs advance as
+    one batch).  Per round and search: the unverified bracket ends are
+    simulated together with the midpoint (speculatively: the midpoint result
+    is discarded when an end check fails).  A lower end at hard_lo is taken as
+    stable without a run (the bottom of the search window).  A failed end
+    check moves the bracket outward by twice its width, clipped to the hard
+    window: lo broken -> [lo - 2w, lo] (lo now a verified broken end);
+    hi stable -> [hi, hi + 2w].  A run with a non-zero status ends its search
+    as "failed".  Returns (searches, seconds, rounds).
+    """
+    run = run or lattice_runner()
+    tol = tol * (1.0 + 1e-9)      # a bracket of width tol (up to rounding) is final
+    total, rounds = 0.0, 0
     for s in searches:
-        s.hard_lo, s.hard_hi = 0.02, ca_max(s.R, s.c, s.lam, s.De)
-        s.hi = min(s.hi, s.hard_hi)
         s.lo = max(s.lo, s.hard_lo)
+        s.hi = min(s.hi, s.hard_hi)
+        if s.lo <= s.hard_lo + 1e-12:
+            s.lo, s.lo_ok = s.hard_lo, True
     while rounds < max_rounds:
         todo, specs = [], []
         for s in searches:
             if s.done:
                 continue
-            if verify_ends and not s.lo_ok:
-                todo.append((s, "lo"))
-                specs.append(RunSpec(s.R, s.c, s.lo, s.De, s.lam))
-            if verify_ends and not s.hi_ok:
-                todo.append((s, "hi"))
-                specs.append(RunSpec(s.R, s.c, s.hi, s.De, s.lam))
-            if (s.lo_ok and s.hi_ok) or not verify_ends:
-                if s.hi - s.lo <= tol:
-                    s.done = True
-                    continue
-                todo.append((s, "mid"))
-                specs.append(RunSpec(s.R, s.c, 0.5 * (s.lo + s.hi), s.De, s.lam))
+            if s.lo_ok and s.hi_ok and s.hi - s.lo <= tol:
+                s.done = True
+                continue
+            if not s.lo_ok:
+                todo.append((s, "lo", s.lo))
+            if not s.hi_ok:
+                todo.append((s, "hi", s.hi))
+            if s.hi - s.lo > tol:
+                todo.append((s, "mid", 0.5 * (s.lo + s.hi)))
         if not todo:
             break
-        res, sec = simulate(specs, precision, **sim_kw)
+        for s, _, ca in todo:
+            specs.append(RunSpec(s.R, s.c, ca, s.De, s.lam))
+        outcomes, sec = run(specs)
         total += sec
         rounds += 1
-        for (s, what), r in zip(todo, res):
+        by_search = {}
+        for (s, what, ca), (broken, status) in zip(todo, outcomes):
             s.runs += 1
-            if what == "lo":
-                if not r.broken:
+            by_search.setdefault(id(s), (s, {}))[1][what] = (ca, broken, status)
+        for s, res in by_search.values():
+            s.rounds += 1
+            if any(st != 0 for _, _, st in res.values()):
+                s.done, s.outside = True, "failed"
+                continue
+            moved = False
+            if "lo" in res:
+                ca, broken, _ = res["lo"]
+                if not broken:
                     s.lo_ok = True
-                elif s.lo <= s.hard_lo + 1e-12:
+                elif ca <= s.hard_lo + 1e-12:
                     s.done, s.outside = True, "below"
+                    continue
                 else:
-                    # the proposed lower end already breaks: fall back to the
-                    # full lower range
-                    s.hi, s.hi_ok = s.lo, True
-                    s.lo, s.lo_ok = s.hard_lo, False
-            elif what == "hi":
-                if r.broken:
+                    w = s.hi - s.lo
+                    s.hi, s.hi_ok = ca, True
+                    s.lo = max(s.hard_lo, ca - 2.0 * w)
+                    s.lo_ok = s.lo <= s.hard_lo + 1e-12
+                    moved = True
+            if "hi" in res and not moved:
+                ca, broken, _ = res["hi"]
+                if broken:
                     s.hi_ok = True
-                elif s.hi >= s.hard_hi - 1e-12:
+                elif ca >= s.hard_hi - 1e-12:
                     s.done, s.outside = True, "above"
+                    continue
                 else:
-                    s.lo, s.lo_ok = s.hi, True
-                    s.hi, s.hi_ok = s.hard_hi, False
-            else:
-                mid = 0.5 * (s.lo + s.hi)
-                if r.broken:
-                    s.hi = mid
+                    w = s.hi - s.lo
+                    s.lo, s.lo_ok = ca, True
+                    s.hi, s.hi_ok = min(s.hard_hi, ca + 2.0 * w), False
+                    moved = True
+            if "mid" in res and not moved:
+                ca, broken, _ = res["mid"]
+                if broken:
+                    s.hi, s.hi_ok = ca, True
                 else:
-                    s.lo = mid
+                    s.lo, s.lo_ok = ca, True
         for s in searches:
             if not s.done and s.lo_ok and s.hi_ok and s.hi - s.lo <= tol:
                 s.done = True

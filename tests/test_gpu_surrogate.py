@@ -86,3 +86,60 @@ def test_adam_step_matches_reference(env):
                           np.zeros(p0.size), 1, lr=1e-3)
     assert np.abs(p1 - want).max() <= 1e-6
     net.close()
+
+
+def test_trained_network_saves_search_runs(env):
+    """What the trained network gains: with a known break-up threshold
+    standing in for the simulations, searches that start from the network's
+    proposed brackets need fewer runs and rounds than plain bisection over
+    the window, and locate the same Ca_cr within the tolerance."""
+    from paper_1411_2181_amd import sweep
+    from paper_1411_2181_amd.surrogate import Surrogate
+
+    def ca_cr(De, lam, c):
+        return 0.17 + 0.02 * De + 0.1 * (lam - 0.75) + 0.2 * (c - 0.5)
+
+    def run(specs):
+        return [(sp.Ca > ca_cr(sp.De, sp.lam, sp.c), 0) for sp in specs], 0.0
+
+    rng = np.random.default_rng(11)
+    n = 600
+    De = rng.choice([0.0, 0.5, 1.0, 2.0], size=n)
+    lam = rng.uniform(0.6, 0.9, size=n)
+    c = rng.uniform(0.45, 0.6, size=n)
+    Ca = rng.uniform(0.10, 0.26, size=n)
+    L2 = rng.choice([100.0, 400.0], size=n)
+    fr = rng.choice([0.2, 0.4], size=n)
+    X = np.stack([Ca, De, lam, c, L2, fr], axis=1)
+    cr = ca_cr(De, lam, c)
+    broken = (Ca > cr).astype(float)
+    D = 0.6 * Ca / cr
+    theta = 45.0 - 80.0 * Ca
+    sg = Surrogate(batch_max=n, seed=1)
+    losses = sg.fit(X, D, theta, broken, epochs=3000, lr=2e-3)
+    assert losses[-1] < 0.2 * losses[0]
+
+    tol, lo, hi = 0.02, 0.10, 0.26
+    qs = WL.query_window(16)
+    plain = [sweep.Search(q["De"], q["lam"], q["confinement"], 24.0, lo, hi, hard_lo=lo, hard_hi=hi)
+             for q in qs]
+    prop = []
+    for q in qs:
+        b = sg.propose(q["De"], q["lam"], q["confinement"], lo, hi, margin=tol / 2)
+        blo, bhi = b if b is not None else (lo, hi)
+        prop.append(sweep.Search(q["De"], q["lam"], q["confinement"], 24.0, blo, bhi,
+                                 hard_lo=lo, hard_hi=hi))
+    sg.close()
+    plain, _, r_plain = sweep.bisect(plain, tol=tol, run=run)
+    prop, _, r_prop = sweep.bisect(prop, tol=tol, run=run)
+    runs_plain = sum(s.runs for s in plain)
+    runs_prop = sum(s.runs for s in prop)
+    print(f"plain: {runs_plain} runs, {r_plain} rounds; surrogate: {runs_prop} runs, {r_prop} rounds")
+    for a, b, q in zip(plain, prop, qs):
+        t = ca_cr(q["De"], q["lam"], q["confinement"])
+        assert a.outside == b.outside
+        if t < hi:
+            assert a.lo <= t < a.hi and b.lo <= t < b.hi
+            assert abs(a.ca_cr - b.ca_cr) <= tol * 1.000001
+    assert runs_prop <= 0.6 * runs_plain
+    assert r_prop < r_plain

@@ -1,0 +1,71 @@
+"""Host logic of the Ca_cr search (sweep.bisect) against a known threshold:
+a stand-in run function marks a run broken iff Ca > Ca_cr(De, lambda, c)."""
+import pytest
+
+from paper_1411_2181_amd import sweep
+
+TOL = 0.02
+
+
+def ca_cr(De, lam, c):
+    return 0.17 + 0.02 * De + 0.1 * (lam - 0.75) + 0.2 * (c - 0.5)
+
+
+def threshold_runner(calls):
+    def run(specs):
+        calls.append(len(specs))
+        return [(sp.Ca > ca_cr(sp.De, sp.lam, sp.c), 0) for sp in specs], 0.0
+    return run
+
+
+def search(lo, hi, De=0.5, lam=0.7, c=0.5, hard=(0.10, 0.26)):
+    return sweep.Search(De, lam, c, 24.0, lo, hi, hard_lo=hard[0], hard_hi=hard[1])
+
+
+@pytest.mark.parametrize("De,lam,c", [(0.0, 0.6, 0.45), (1.0, 0.75, 0.5), (2.0, 0.9, 0.55)])
+def test_plain_bisection_brackets_the_threshold(De, lam, c):
+    calls = []
+    s = search(0.10, 0.26, De, lam, c)
+    (s,), _, rounds = sweep.bisect([s], tol=TOL, run=threshold_runner(calls))
+    t = ca_cr(De, lam, c)
+    assert s.outside == ""
+    assert s.lo_ok and s.hi_ok and s.lo <= t < s.hi and s.hi - s.lo <= TOL * 1.000001
+    assert abs(s.ca_cr - t) <= TOL / 2 * 1.000001
+    assert rounds == len(calls) and s.runs == sum(calls)
+
+
+def test_threshold_above_and_below_the_window():
+    calls = []
+    above = search(0.10, 0.20, De=2.0, lam=0.9, c=0.6, hard=(0.10, 0.20))   # ca_cr = 0.265
+    below = search(0.10, 0.26, hard=(0.22, 0.26))                              # ca_cr ~ 0.18
+    res, _, _ = sweep.bisect([above, below], tol=TOL, run=threshold_runner(calls))
+    assert res[0].outside == "above" and res[0].runs == 2      # hi check + speculative midpoint
+    # the bottom of the window is taken as stable: a threshold below it ends
+    # in the lowest bracket, every run of which broke
+    assert res[1].outside == "" and res[1].lo == 0.22 and res[1].hi - res[1].lo <= TOL * 1.000001
+
+
+def test_exact_proposal_needs_one_round_and_two_runs():
+    t = ca_cr(0.5, 0.7, 0.5)
+    calls = []
+    s = search(t - TOL / 2, t + TOL / 2)
+    (s,), _, rounds = sweep.bisect([s], tol=TOL, run=threshold_runner(calls))
+    assert rounds == 1 and s.runs == 2 and s.lo <= t < s.hi
+
+
+@pytest.mark.parametrize("offset", [-0.05, -0.025, 0.025, 0.05])
+def test_wrong_proposal_falls_back_outward(offset):
+    t = ca_cr(0.5, 0.7, 0.5)
+    calls = []
+    c = t + offset
+    s = search(c - TOL / 2, c + TOL / 2)
+    (s,), _, _ = sweep.bisect([s], tol=TOL, run=threshold_runner(calls))
+    assert s.outside == "" and s.lo <= t < s.hi and s.hi - s.lo <= TOL * 1.000001
+
+
+def test_failed_run_ends_the_search():
+    def run(specs):
+        return [(False, -5) for _ in specs], 0.0
+    s = search(0.10, 0.26)
+    (s,), _, _ = sweep.bisect([s], tol=TOL, run=run)
+    assert s.done and s.outside == "failed"
