@@ -106,10 +106,11 @@ def gpu_run(precision, steps, warmup, launch=None):
                 info=info, launch=launch, tuned=tuned)
 
 
-def pmc_pass(precision, steps=4):
+def pmc_pass(precision, steps=4, launch=None):
     """Short run for hardware-counter collection: a 1 GiB device-to-device copy
     (the reference of known size for scaling FETCH_SIZE / WRITE_SIZE), then a
-    few eager steps of the workload with every pass as its own dispatch."""
+    few eager steps of the workload with every pass as its own dispatch (after
+    the autotuner's candidates, unless ``launch`` pins the shape)."""
     import torch
     from paper_1411_2181_amd import autotune, lbmve
     a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -121,7 +122,10 @@ def pmc_pass(precision, steps=4):
     del a, b, flush
     p, _ = workload_params()
     s = lbmve.Solver(p, precision)
-    autotune.tune(s, steps=2, use_cache=False, save=False)
+    if launch:
+        s.set_launch(**launch)
+    else:
+        autotune.tune(s, steps=2, use_cache=False, save=False)
     s.step_profiled(steps)
     s.close()
 
@@ -210,7 +214,7 @@ def main():
     import torch
     torch.cuda.set_device(0)
     if args.pmc_pass:
-        pmc_pass(args.precision)
+        pmc_pass(args.precision, launch=launch)
         return
 
     r = gpu_run(args.precision, args.steps, args.warmup, launch)

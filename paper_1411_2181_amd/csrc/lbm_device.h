@@ -86,14 +86,6 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
   h ^= h >> 16;
   return h;
 }
-// Marsaglia's xorshift32 step: further words from one hashed seed.
-__device__ __forceinline__ uint32_t xorshift32(uint32_t x) {
-  x ^= x << 13;
-  x ^= x >> 17;
-  x ^= x << 5;
-  return x;
-}
-
 template <typename T>
 struct Store<T, T> {
   static constexpr bool kRandom = false;
@@ -130,7 +122,7 @@ struct Store<float, __half> {
     p[k] = h;
 #endif
   }
-  // Stochastic rounding to FP16 with 13 random bits r (bits 0..12): adding r
+  // Stochastic rounding to FP16 with 13 random bits r (r < 2^13): adding r
   // to the 13 float mantissa bits that FP16 drops and then truncating them
   // rounds |v| up with probability (|v| - lower)/spacing, so the rounding
   // error has zero mean.  Deterministic rounding leaves the same error at
@@ -142,7 +134,7 @@ struct Store<float, __half> {
     (void)r;
     const __half h = __float2half_rn(v);
 #else
-    const uint32_t b = (__float_as_uint(v) + (r & 0x1fffu)) & 0xffffe000u;
+    const uint32_t b = (__float_as_uint(v) + r) & 0xffffe000u;
     const __half h = __float2half_rn(__uint_as_float(b));
 #endif
     raw_store(p, k, h);

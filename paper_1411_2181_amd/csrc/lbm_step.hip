@@ -34,12 +34,13 @@
 
 namespace lbm {
 
-// Equilibrium minus its rest part, f^eq_i - w_i rho: the shifted equilibrium.
+// Equilibrium minus its rest part, f^eq_i - w_i rho (the shifted
+// equilibrium), times a power-of-two storage scale folded into the weight.
 template <typename T>
-__device__ __forceinline__ T geq(int i, T rho, T ux, T uy, T uz) {
+__device__ __forceinline__ T geq(int i, T rho, T ux, T uy, T uz, T scale) {
   const T cu = T(CX[i]) * ux + T(CY[i]) * uy + T(CZ[i]) * uz;
   const T usq = ux * ux + uy * uy + uz * uz;
-  return wgt<T>(i) * rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
+  return (wgt<T>(i) * scale) * rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
 }
 
 __device__ __forceinline__ int64_t nid(int x, int y, int z, int nx, int ny) {
@@ -256,19 +257,30 @@ __global__ void __launch_bounds__(BX * BY) LBM_COLLIDE_OCC k_collide(StepArgs<T,
         sl[k] = rec[nid(gx, gy, zp, nx, ny)];
       }
     };
+    // Byte offsets inside one direction array (a run's array is < 4 GiB, which
+    // the library checks): the plane term is uniform, rows and columns
+    // (periodic) are per thread, and the array base is uniform, so every
+    // population access is a uniform base plus one 32-bit offset.
+    constexpr uint32_t SB = sizeof(S);
+    const uint32_t pb = (uint32_t)nx * (uint32_t)ny * SB;
+    const uint32_t rowb[3] = {(uint32_t)(ym * nx) * SB, (uint32_t)(y * nx) * SB,
+                              (uint32_t)(yp * nx) * SB};
+    const uint32_t colb[3] = {(uint32_t)xm * SB, (uint32_t)x * SB, (uint32_t)xp * SB};
+    auto arr = [&](const S* base, int i, uint32_t off) {
+      return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base + (int64_t)i * N) + off);
+    };
     // the populations that arrive at (x, y, zz): pulled from x - c_i, or the
     // node's own opposite population where the link crosses a wall
     auto load_plane = [&](int zz, T (&v)[Q]) {
-      const int64_t m = nid(x, y, zz, nx, ny);
+      const uint32_t own = (uint32_t)zz * pb + rowb[1] + colb[1];
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         const int zs = zz - CZ[i];
         if (CZ[i] == 0 || (zs >= 0 && zs < nz)) {
-          const int xs = CX[i] > 0 ? xm : (CX[i] < 0 ? xp : x);
-          const int ys = CY[i] > 0 ? ym : (CY[i] < 0 ? yp : y);
-          v[i] = St::load(fs + (int64_t)i * N, nid(xs, ys, zs, nx, ny));
+          const uint32_t off = (uint32_t)zs * pb + rowb[1 - CY[i]] + colb[1 - CX[i]];
+          v[i] = St::load(arr(fs, i, off), 0);
         } else {
-          v[i] = St::load(fs + (int64_t)OPPI[i] * N, m);
+          v[i] = St::load(arr(fs, OPPI[i], own), 0);
         }
       }
     };
@@ -277,16 +289,15 @@ __global__ void __launch_bounds__(BX * BY) LBM_COLLIDE_OCC k_collide(StepArgs<T,
     if (tl.z0 > 0) stage(tl.z0 - 1);
     stage(tl.z0);
     // software pipeline: the populations of plane z+1 are in flight while
-    // plane z is collided
-    T cur[Q];
-    if (active) load_plane(tl.z0, cur);
-    for (int z = tl.z0; z < zend; ++z) {
-      T nxt[Q];
+    // plane z is collided; the two register sets alternate roles (the march
+    // is unrolled by two planes), so no copy is made between planes
+    auto plane = [&](int z, T (&cur)[Q], T (&nxt)[Q]) {
       if (active && z + 1 < zend) load_plane(z + 1, nxt);
       if (z + 1 < nz) stage(z + 1);
       __syncthreads();
       if (active) {
         const int64_t n = nid(x, y, z, nx, ny);
+        const uint32_t nb = (uint32_t)z * pb + rowb[1] + colb[1];   // n * sizeof(S)
         const int lc = (ty + 1) * HX + (tx + 1);
         // BGK collision of each arriving population in the shifted variable
         // of the node that holds it (the record's node in both branches),
@@ -303,7 +314,7 @@ __global__ void __launch_bounds__(BX * BY) LBM_COLLIDE_OCC k_collide(StepArgs<T,
           const int zs = z - CZ[i];
           if (CZ[i] == 0 || (zs >= 0 && zs < nz)) {
             const V4<T> r = ring[zs & 3][lc - CY[i] * HX - CX[i]];
-            cur[i] = cur[i] - (cur[i] - geq<T>(i, r.x * kS, r.y, r.z, r.w)) * it;
+            cur[i] = cur[i] - (cur[i] - geq<T>(i, r.x, r.y, r.z, r.w, kS)) * it;
             if (i != 0) cur[i] += (wgt<T>(i) * kS) * (r.x - rx);
           } else {
             // half-way bounce-back: the population that left x in direction
@@ -311,7 +322,7 @@ __global__ void __launch_bounds__(BX * BY) LBM_COLLIDE_OCC k_collide(StepArgs<T,
             const int o = OPPI[i];
             const V4<T> r = ring[z & 3][lc];
             const T uwall = CZ[o] > 0 ? uw : -uw;
-            cur[i] = cur[i] - (cur[i] - geq<T>(o, r.x * kS, r.y, r.z, r.w)) * it
+            cur[i] = cur[i] - (cur[i] - geq<T>(o, r.x, r.y, r.z, r.w, kS)) * it
                      - ((T(6) * kS * wgt<T>(o)) * r.x) * (T(CX[o]) * uwall);
           }
           drho += cur[i];
@@ -319,19 +330,20 @@ __global__ void __launch_bounds__(BX * BY) LBM_COLLIDE_OCC k_collide(StepArgs<T,
         const T rsum = rx + drho * ikS;
         // stored: f*_i - w_i rho_x_new = h_i - w_i drho; the momentum is
         // summed from the values as stored (the rest parts cancel pairwise
-        // in sum_i c_i w_i).  FP16 rounding draws 13 random bits per value
-        // from a hash of (node, component, step): independent of the tile
-        // shape and batch layout, and reproducible.
-        uint32_t rw = 0;
+        // in sum_i c_i w_i).  FP16 rounding takes 13 random bits per value:
+        // a hash of (node, component, step) starts a Weyl sequence over the
+        // directions (uniform for every direction, independent of the tile
+        // shape and batch layout, and reproducible).
+        uint32_t hb = 0;
         if (St::kRandom)
-          rw = fmix32((uint32_t)n * 0x9e3779b1u ^ fmix32((uint32_t)(R.base + g) * 2u + (uint32_t)s));
+          hb = fmix32((uint32_t)n * 0x9e3779b1u ^ ((uint32_t)(R.base + g) * 2u + (uint32_t)s) * 0x85ebca77u);
         T jx = 0, jy = 0, jz = 0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          if (St::kRandom && i > 0 && (i & 1) == 0) rw = xorshift32(rw);
-          const uint32_t rb = (i & 1) ? (rw >> 16) : rw;
+          const uint32_t rb = (hb + (uint32_t)i * 0x9e3779b9u) >> 19;
           const T v = cur[i] - wgt<T>(i) * drho;
-          const T fq = St::put(fo + (int64_t)i * N, n, v, rb);
+          S* dst = reinterpret_cast<S*>(reinterpret_cast<char*>(fo + (int64_t)i * N) + nb);
+          const T fq = St::put(dst, 0, v, rb);
           if (CX[i] != 0) jx += T(CX[i]) * fq;
           if (CY[i] != 0) jy += T(CY[i]) * fq;
           if (CZ[i] != 0) jz += T(CZ[i]) * fq;
@@ -345,8 +357,12 @@ __global__ void __launch_bounds__(BX * BY) LBM_COLLIDE_OCC k_collide(StepArgs<T,
         j_out[2 * N + n] = jz;
         if (!isfinite(rsum + jx + jy + jz)) atomicOr(a.P.status + tl.run, ST_NAN);
       }
-#pragma unroll
-      for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
+    };
+    T va[Q], vb[Q];
+    if (active) load_plane(tl.z0, va);
+    for (int z = tl.z0; z < zend; z += 2) {
+      plane(z, va, vb);
+      if (z + 1 < zend) plane(z + 1, vb, va);
     }
   }
 }

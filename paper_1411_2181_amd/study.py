@@ -95,6 +95,13 @@ def single_runner(precision: str, log=None):
     return run
 
 
+def _plain(o):
+    """JSON form of NumPy scalars and tuples inside the report."""
+    if isinstance(o, np.generic):
+        return o.item()
+    raise TypeError(type(o))
+
+
 def cmd_generate(args, log):
     specs = sample_specs(args.runs + args.skip)[args.skip:]
 
@@ -215,7 +222,7 @@ def cmd_search(args, log):
                                                      sweeps_per_hour=n64 / t64 * 3600)
     sg.close()
     with open(args.out, "w") as fh:
-        json.dump(report, fh, indent=1)
+        json.dump(report, fh, indent=1, default=_plain)
     for k in ("plain", "surrogate", "plain_fp64_single"):
         if k in report["search"]:
             log(k + " " + json.dumps(report["search"][k]))
