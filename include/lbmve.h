@@ -84,7 +84,8 @@ enum {
  * 15,16 = +-(0,1,1); 17,18 = +-(0,1,-1).
  */
 typedef struct {
-  int32_t nx, ny, nz;    /* fluid nodes, each >= 3; W = nz                   */
+  int32_t nx, ny, nz;    /* fluid nodes, each >= 3; W = nz; nx*ny*nz < 2^31
+                            and nx*ny*nz*(bytes per stored population) < 2^32 */
   int32_t precision;     /* LBM_FP64 | LBM_FP32 | LBM_FP16S                  */
   double u_wall;         /* top wall +u_wall, bottom wall -u_wall (x); |.|<0.2 */
   double radius;         /* droplet radius R (0 = no droplet); R < nz/2      */

@@ -90,6 +90,16 @@ def test_valid_parameters_and_workspace_size(L):
     assert L.lbm_validate(ctypes.byref(bad)) == lbmve.LBM_EINVAL
 
 
+def test_population_array_must_fit_32bit_offsets(L):
+    """One run's population array is addressed with 32-bit byte offsets:
+    1024 x 1024 x 600 nodes fit as FP32 (2.5 GB) but not as FP64 (5 GB)."""
+    from paper_1411_2181_amd import lbmve
+    d = WL.base_params(nx=1024, ny=1024, nz=600, radius=8.0)
+    assert L.lbm_validate(ctypes.byref(lbmve.make_params(d, "fp32"))) == 0
+    assert L.lbm_validate(ctypes.byref(lbmve.make_params(d, "fp16s"))) == 0
+    assert L.lbm_validate(ctypes.byref(lbmve.make_params(d, "fp64"))) == lbmve.LBM_EINVAL
+
+
 def test_batch_requires_one_precision(L):
     from paper_1411_2181_amd import lbmve
     a = lbmve.make_params(WL.small_newtonian(), "fp32")
