@@ -75,6 +75,7 @@ def measured_traffic(precision, launch):
     entry = t.get(precision)
     if not entry or entry.get("source_hash") != source_hash():
         return None
+    # a persistent grid over the same tiles is taken to move the same bytes
     return entry["launches"].get(f"{launch['bx']}x{launch['by']}x{launch['bz']}")
 
 
@@ -125,7 +126,8 @@ def pmc_pass(precision, steps=4, launch=None):
     if launch:
         s.set_launch(**launch)
     else:
-        autotune.tune(s, steps=2, use_cache=False, save=False)
+        # non-persistent candidates only: their grids identify (bx, by, bz)
+        autotune.tune(s, steps=2, use_cache=False, save=False, persistent=False)
     s.step_profiled(steps)
     s.close()
 
@@ -201,12 +203,12 @@ def main():
     ap.add_argument("--pmc-pass", action="store_true",
                     help="short run for rocprofv3 counter collection (prints no JSON)")
     ap.add_argument("--launch", default="",
-                    help="pin the launch shape BXxBYxBZ instead of autotuning (profiling runs)")
+                    help="pin the launch shape BXxBYxBZ[xP] instead of autotuning (profiling runs)")
     args = ap.parse_args()
     launch = None
     if args.launch:
-        bx, by, bz = (int(v) for v in args.launch.lower().split("x"))
-        launch = dict(bx=bx, by=by, bz=bz, persistent=0)
+        v = [int(t) for t in args.launch.lower().split("x")]
+        launch = dict(bx=v[0], by=v[1], bz=v[2], persistent=v[3] if len(v) > 3 else 0)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; "
                                    "multi-GPU slab decomposition is a design note"}))

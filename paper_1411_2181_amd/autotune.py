@@ -18,6 +18,7 @@ CACHE = os.path.join(_HERE, "autotune_cache.json")
 
 SHAPES = [(64, 4), (32, 8), (128, 2), (64, 2), (32, 4)]
 BZ = [8, 16, 32, 64]
+PERSISTENT = [1024, 2048]
 
 
 def candidates(nz_max: int):
@@ -48,12 +49,13 @@ def _load():
     return {}
 
 
-def tune(batch, steps: int = 4, cands=None, use_cache: bool = True, save: bool = True) -> dict:
+def tune(batch, steps: int = 4, cands=None, use_cache: bool = True, save: bool = True,
+         persistent: bool = True) -> dict:
     """Pick the fastest launch shape for ``batch`` (an lbmve.Batch/Solver),
     apply it and return {"launch": ..., "ms_per_step": ..., "table": [...]}.
 
-    Tuning advances the runs by (len(cands) + 1) * steps steps; callers that
-    need a pristine state tune on a scratch copy."""
+    Tuning advances the runs by (len(cands) + len(PERSISTENT) + 1) * steps
+    steps; callers that need a pristine state tune on a scratch copy."""
     key = _key(batch)
     cache = _load()
     if use_cache and key in cache:
@@ -64,6 +66,14 @@ def tune(batch, steps: int = 4, cands=None, use_cache: bool = True, save: bool =
     table = []
     batch.step_profiled(steps)          # warm-up: graph-free, first-touch
     for c in cands:
+        batch.set_launch(**c)
+        ms = sum(batch.step_profiled(steps)) / steps
+        table.append(dict(launch=c, ms_per_step=ms))
+    best = min(table, key=lambda r: r["ms_per_step"])
+    # persistent grids of the best shape (a few workgroups per CU looping over
+    # the tile table)
+    for pers in (PERSISTENT if persistent else []):
+        c = dict(best["launch"], persistent=pers)
         batch.set_launch(**c)
         ms = sum(batch.step_profiled(steps)) / steps
         table.append(dict(launch=c, ms_per_step=ms))

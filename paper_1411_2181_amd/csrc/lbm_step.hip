@@ -55,6 +55,18 @@ __device__ __forceinline__ int64_t nid(int x, int y, int z, int nx, int ny) {
 #define LBM_COLLIDE_OCC
 #endif
 
+// Planes held in the LDS rings of the force and FENE-P passes.  Three (the
+// minimum for a radius-1 stencil in z) take a second barrier per plane before
+// a slot is overwritten; four need one barrier but 4/3 the LDS, which limits
+// the workgroups per CU.
+#ifndef LBM_RING_SLOTS
+#define LBM_RING_SLOTS 3
+#endif
+constexpr int RS = LBM_RING_SLOTS;
+static_assert(RS == 3 || RS == 4, "ring of 3 or 4 planes");
+// ring slot of plane zp >= -1
+__device__ __forceinline__ int rslot(int zp) { return RS == 4 ? (zp & 3) : (zp + 3) % 3; }
+
 // Shapes of the tile (bx, by) with a compiled instance of every pass.
 #define LBM_FOR_SHAPES(M) M(64, 4) M(32, 8) M(128, 2) M(64, 2) M(32, 4)
 
@@ -69,8 +81,8 @@ template <typename T, typename S, int BX, int BY>
 __global__ void __launch_bounds__(BX * BY) k_force(StepArgs<T, S> a) {
   constexpr int HX = BX + 2, HY = BY + 2, HN = HX * HY, NT = BX * BY;
   constexpr int KP = (HN + NT - 1) / NT;
-  __shared__ T srho[4][2][HN];
-  __shared__ T sT[4][6][HN];
+  __shared__ T srho[RS][2][HN];
+  __shared__ T sT[RS][6][HN];
   const int g = *a.gstep;
   const int tx = (int)threadIdx.x, ty = (int)threadIdx.y, tid = ty * BX + tx;
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
@@ -117,7 +129,7 @@ __global__ void __launch_bounds__(BX * BY) k_force(StepArgs<T, S> a) {
     // T = chi (eta_P/tau_P)(f C - I): chi the clamped rescaled mass fraction
     // of the polymer phase's component, f the Peterlin factor in FP64
     auto store_raw = [&](int zp) {
-      const int sl = zp & 3;
+      const int sl = rslot(zp);
 #pragma unroll
       for (int kk = 0; kk < KP; ++kk) {
         const int k = tid + kk * NT;
@@ -148,6 +160,7 @@ __global__ void __launch_bounds__(BX * BY) k_force(StepArgs<T, S> a) {
     load_raw(tl.z0 + 1);
     const int lc = (ty + 1) * HX + (tx + 1);
     for (int z = tl.z0; z < zend; ++z) {
+      if (RS == 3) __syncthreads();   // plane z-2's slot is free (plane z-1 done)
       store_raw(z + 1);
       if (z + 2 <= zend) load_raw(z + 2);
       const int64_t n = nid(active ? x : 0, active ? y : 0, z, nx, ny);
@@ -162,7 +175,7 @@ __global__ void __launch_bounds__(BX * BY) k_force(StepArgs<T, S> a) {
       T sA0 = 0, sA1 = 0, sA2 = 0, sB0 = 0, sB1 = 0, sB2 = 0;
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
-        const int sl = (z + CZ[i]) & 3;
+        const int sl = rslot(z + CZ[i]);
         const int k = lc + CY[i] * HX + CX[i];
         const T nA = srho[sl][0][k], nB = srho[sl][1][k];
         const T wt = T(3) * wgt<T>(i);
@@ -170,7 +183,7 @@ __global__ void __launch_bounds__(BX * BY) k_force(StepArgs<T, S> a) {
         if (CY[i] != 0) { sA1 += (wt * T(CY[i])) * nB; sB1 += (wt * T(CY[i])) * nA; }
         if (CZ[i] != 0) { sA2 += (wt * T(CZ[i])) * nB; sB2 += (wt * T(CZ[i])) * nA; }
       }
-      const int s0 = z & 3, sp = (z + 1) & 3, sm = (z - 1) & 3;
+      const int s0 = rslot(z), sp = rslot(z + 1), sm = rslot(z - 1);
       const T rA = srho[s0][0][lc], rB = srho[s0][1][lc];
       T FA0 = -G * rA * sA0, FA1 = -G * rA * sA1, FA2 = -G * rA * sA2;
       T FB0 = -G * rB * sB0, FB1 = -G * rB * sB1, FB2 = -G * rB * sB2;
@@ -376,8 +389,8 @@ template <typename T, typename S, int BX, int BY>
 __global__ void __launch_bounds__(BX * BY) k_fene(StepArgs<T, S> a) {
   constexpr int HX = BX + 2, HY = BY + 2, HN = HX * HY, NT = BX * BY;
   constexpr int KP = (HN + NT - 1) / NT;
-  __shared__ T sC[4][6][HN];
-  __shared__ T sU[4][3][HN];
+  __shared__ T sC[RS][6][HN];
+  __shared__ T sU[RS][3][HN];
   const int g = *a.gstep;
   const int tx = (int)threadIdx.x, ty = (int)threadIdx.y, tid = ty * BX + tx;
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
@@ -415,7 +428,7 @@ __global__ void __launch_bounds__(BX * BY) k_fene(StepArgs<T, S> a) {
       }
     };
     auto store_raw = [&](int zp) {
-      const int sl = zp & 3;
+      const int sl = rslot(zp);
 #pragma unroll
       for (int kk = 0; kk < KP; ++kk) {
         const int k = tid + kk * NT;
@@ -447,12 +460,13 @@ __global__ void __launch_bounds__(BX * BY) k_fene(StepArgs<T, S> a) {
     const int lc = (ty + 1) * HX + (tx + 1);
     uint32_t st = 0;
     for (int z = tl.z0; z < zend; ++z) {
+      if (RS == 3) __syncthreads();   // plane z-2's slot is free (plane z-1 done)
       store_raw(z + 1);
       if (z + 2 <= zend) load_raw(z + 2);
       __syncthreads();
       if (!active) continue;
       const int64_t n = nid(x, y, z, nx, ny);
-      const int s0 = z & 3, sp = (z + 1) & 3, sm = (z - 1) & 3;
+      const int s0 = rslot(z), sp = rslot(z + 1), sm = rslot(z - 1);
       const T u0 = sU[s0][0][lc], u1 = sU[s0][1][lc], u2 = sU[s0][2][lc];
       T Gm[3][3];
 #pragma unroll

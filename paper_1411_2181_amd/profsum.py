@@ -78,13 +78,14 @@ def copy_reference(path):
     return best[1]
 
 
-def trace_table(path, box, tail=0):
+def trace_table(path, box, tail=0, label=None):
     """Mean durations per (kernel, launch); ``tail`` > 0 keeps only the last
     ``tail`` dispatches of each (bench.py ends with that many eager steps
-    timed by HIP events, after the graph-replayed region)."""
+    timed by HIP events, after the graph-replayed region).  ``label`` names
+    the launch of a pinned run (a persistent grid does not encode bz)."""
     groups = defaultdict(list)
     for kind, key, dur, _ in step_dispatches(path, box):
-        groups[(kind, key)].append(dur)
+        groups[(kind, label or key)].append(dur)
     rows = []
     for (kind, key), d in groups.items():
         if tail > 0:
@@ -127,6 +128,7 @@ def main(argv=None):
     t.add_argument("csv")
     t.add_argument("--box", default="512,256,128")
     t.add_argument("--tail", type=int, default=0)
+    t.add_argument("--launch", default=None, help="label of the pinned launch shape")
     p = sub.add_parser("traffic")
     p.add_argument("fetch_csv")
     p.add_argument("write_csv")
@@ -138,7 +140,7 @@ def main(argv=None):
     if a.cmd == "trace":
         print("| kernel | launch (bx x by x bz) | calls | mean us | min us | max us |")
         print("|---|---|---|---|---|---|")
-        for r in trace_table(a.csv, box, a.tail):
+        for r in trace_table(a.csv, box, a.tail, a.launch):
             print(f"| {r['kernel']} | {r['launch']} | {r['calls']} | {r['mean_us']:.1f} | "
                   f"{r['min_us']:.1f} | {r['max_us']:.1f} |")
         return 0

@@ -2,7 +2,7 @@
 then proposes Ca_cr brackets; plain bisection on the same GPU is the
 reference.
 
-    python -m paper_1411_2181_amd.study generate DATA.json [--runs 160] [--skip 0]
+    python -m paper_1411_2181_amd.study generate DATA.json [--runs 160] [--skip 0] [--near D1.json]
     python -m paper_1411_2181_amd.study search OUT.json --data DATA.json[,DATA2.json] \
         [--queries 16] [--fp64-queries 1]
 
@@ -16,11 +16,14 @@ stability), De in {0, 0.5, 1, 2}, L^2 in {100, 400}, polymer fraction in
 the U_w = 0.19 cap.  Each run lasts up to T_END steps and is checked for
 break-up every EVERY steps (a run stops once it breaks).
 
+Training data: a first batch from the window sampler, then (``--near``) a
+batch placed where the network trained on the first one is uncertain.
+
 Searches: tolerance 0.02 (Ca_cr located within +-0.01), window
 [CA_LO, Ca_max] with CA_LO taken as stable.  Plain bisection starts from the
-window; the surrogate's search starts from a bracket of width 0.02 around
-the Ca where its break-up logit crosses zero and falls back outward when a
-bracket end fails (sweep.bisect).  Both advance every query's runs of a round
+window; the surrogate's search starts from the network's bracket (centred
+where its break-up probability crosses 1/2, at least +-0.02 wide) and falls
+back outward when a bracket end fails (sweep.bisect).  Both advance every query's runs of a round
 as one batch (FP32).  The plain FP64 one-run-at-a-time variant is timed on
 ``--fp64-queries`` triples.
 """
@@ -90,7 +93,8 @@ def single_runner(precision: str, log=None):
         for sp in specs:
             res, sec = sweep.simulate([sp], precision, t_end=T_END, every=EVERY, progress=log)
             total += sec
-            out.append((res[0].broken, res[0].status))
+            r = res[0]
+            out.append((r.broken, r.status, r.steps * r.params["nx"] * r.params["ny"] * r.params["nz"]))
         return out, total
     return run
 
@@ -102,13 +106,35 @@ def _plain(o):
     raise TypeError(type(o))
 
 
+def near_boundary_specs(n, data_paths, base_seed=55555, pool=4000, band=(0.15, 0.85), log=print):
+    """Active-learning batch: train the network on earlier runs, then keep,
+    in sampler order, the first n window samples whose predicted break-up
+    probability lies in ``band`` (where the boundary is still uncertain)."""
+    data = load_data(data_paths)
+    ok = [r for r in data["rows"] if r["status"] == 0]
+    sg = Surrogate(batch_max=max(4096, len(ok), pool), seed=1)
+    sg.fit(np.array([r["inputs"] for r in ok]), np.array([r["D"] for r in ok]),
+           np.array([r["theta"] for r in ok]), np.array([r["broken"] for r in ok], dtype=float),
+           epochs=3000, lr=2e-3)
+    cands = sample_specs(pool, base_seed)
+    p = sg.predict(np.array([sp.inputs() for sp in cands]))[2]
+    sg.close()
+    keep = [sp for sp, pk in zip(cands, p) if band[0] < pk < band[1]][:n]
+    log(f"near-boundary batch: {len(keep)} of {pool} candidates with p in {band}")
+    return keep
+
+
 def cmd_generate(args, log):
-    specs = sample_specs(args.runs + args.skip)[args.skip:]
+    if args.near:
+        specs = near_boundary_specs(args.runs, args.near.split(","), log=log)
+    else:
+        specs = sample_specs(args.runs + args.skip)[args.skip:]
 
     def save(rows, sec, upd):
         with open(args.out, "w") as fh:
             json.dump(dict(window=dict(R=24.0, ca_lo=CA_LO, t_end=T_END, every=EVERY),
-                           first_run=args.skip, seconds=sec, updates=upd, rows=rows), fh, indent=1)
+                           first_run=args.skip, near=args.near, seconds=sec, updates=upd,
+                           rows=rows), fh, indent=1, default=_plain)
 
     generate(specs, log=log, save=save)
     return 0
@@ -179,10 +205,13 @@ def cmd_search(args, log):
     prop, proposals = [], []
     for q in qs:
         lo, hi = window(q)
-        b = sg.propose(q["De"], q["lam"], q["c"], lo, hi, margin=TOL / 2)
+        b = sg.propose(q["De"], q["lam"], q["c"], lo, hi, tol=TOL)
         proposals.append(b)
+        # no predicted crossing: check the top of the window first (one run);
+        # if it breaks after all, the search goes on as plain bisection
         blo, bhi = b if b is not None else (lo, hi)
-        prop.append(sweep.Search(q["De"], q["lam"], q["c"], q["R"], blo, bhi, hard_lo=lo, hard_hi=hi))
+        prop.append(sweep.Search(q["De"], q["lam"], q["c"], q["R"], blo, bhi, hard_lo=lo, hard_hi=hi,
+                                 speculate=b is not None))
     prop, t_sg, r_sg = sweep.bisect(prop, tol=TOL,
                                     run=sweep.lattice_runner("fp32", log=log, t_end=T_END, every=EVERY))
     log(f"surrogate-bracketed: {t_sg:.1f} s, {r_sg} rounds, {sum(s.runs for s in prop)} runs")
@@ -191,19 +220,28 @@ def cmd_search(args, log):
     for q, a, b, pb in zip(qs, plain, prop, proposals):
         rows_q.append(dict(q, window=list(window(q)), proposal=pb,
                            plain=dict(ca_cr=a.ca_cr, bracket=[a.lo, a.hi], outside=a.outside,
-                                      runs=a.runs, rounds=a.rounds),
+                                      runs=a.runs, rounds=a.rounds, updates=a.updates),
                            surrogate=dict(ca_cr=b.ca_cr, bracket=[b.lo, b.hi], outside=b.outside,
-                                          runs=b.runs, rounds=b.rounds)))
+                                          runs=b.runs, rounds=b.rounds, updates=b.updates)))
         if a.outside == b.outside:
             comparable += 1
             agree += (a.outside != "" or abs(a.ca_cr - b.ca_cr) <= TOL)
+    # sweeps per hour at saturation: with many queries in flight the GPU is
+    # full and time goes as lattice updates (batched FP32 rate of the data
+    # generation), not as rounds
+    rate = data["updates"] / data["seconds"]
+    upd_plain = sum(s.updates for s in plain)
+    upd_sg = sum(s.updates for s in prop)
     report["search"] = dict(
         queries=len(qs), tol=TOL, t_end=T_END,
         plain=dict(seconds=t_plain, rounds=r_plain, runs=sum(s.runs for s in plain),
-                   sweeps_per_hour=len(qs) / t_plain * 3600),
+                   updates=upd_plain, sweeps_per_hour=len(qs) / t_plain * 3600,
+                   sweeps_per_hour_saturated=len(qs) / (upd_plain / rate) * 3600),
         surrogate=dict(seconds=t_sg, rounds=r_sg, runs=sum(s.runs for s in prop),
-                       sweeps_per_hour=len(qs) / t_sg * 3600,
+                       updates=upd_sg, sweeps_per_hour=len(qs) / t_sg * 3600,
+                       sweeps_per_hour_saturated=len(qs) / (upd_sg / rate) * 3600,
                        first_round_hits=sum(1 for s in prop if s.rounds == 1 and s.outside == "")),
+        batched_fp32_rate_mlups=rate / 1e6,
         same_outcome=comparable, agree_within_tol=agree, rows=rows_q)
 
     # plain FP64, one run at a time, on the first triples
@@ -237,6 +275,8 @@ def main(argv=None):
     g.add_argument("out")
     g.add_argument("--runs", type=int, default=160)
     g.add_argument("--skip", type=int, default=0, help="start at this run of the sampler sequence")
+    g.add_argument("--near", default="", help="earlier generate outputs: place the runs where "
+                                              "the network trained on them is uncertain")
     s = sub.add_parser("search")
     s.add_argument("out")
     s.add_argument("--data", required=True, help="comma-separated generate outputs")

@@ -75,22 +75,37 @@ class Surrogate:
         p = 1.0 / (1.0 + np.exp(-z[:, 2]))
         return z[:, 0], 45.0 * z[:, 1], p
 
-    def propose(self, De, lam, c, lo, hi, L2=100.0, fraction=0.4, margin=0.02, grid=256):
-        """Bracket [Ca_lo, Ca_hi] around the predicted break-up boundary
-        (logit = 0) on [lo, hi], widened by ``margin`` on each side; None if
-        the network predicts no crossing in the range."""
+    def breakup_probability(self, Ca, De, lam, c, L2=100.0, fraction=0.4):
+        Ca = np.atleast_1d(np.asarray(Ca, dtype=np.float64))
+        X = np.stack([Ca, np.full(Ca.size, De), np.full(Ca.size, lam), np.full(Ca.size, c),
+                      np.full(Ca.size, L2), np.full(Ca.size, fraction)], axis=1)
+        return self.predict(X)[2]
+
+    def propose(self, De, lam, c, lo, hi, tol=0.02, L2=100.0, fraction=0.4, grid=512):
+        """Bracket around the predicted break-up boundary on [lo, hi]: centred
+        where the break-up probability crosses 1/2, half-width the larger of
+        tol and half the distance between its 1/4 and 3/4 crossings (the
+        network's own uncertainty), clipped to [lo, hi].  None when the
+        network predicts no crossing in the range."""
         ca = np.linspace(lo, hi, grid)
-        X = np.stack([ca, np.full(grid, De), np.full(grid, lam), np.full(grid, c),
-                      np.full(grid, L2), np.full(grid, fraction)], axis=1)
-        _, _, p = self.predict(X)
-        above = np.nonzero(p >= 0.5)[0]
-        if above.size == 0:
+        p = self.breakup_probability(ca, De, lam, c, L2, fraction)
+
+        def crossing(level):
+            above = np.nonzero(p >= level)[0]
+            if above.size == 0:
+                return None
+            k = above[0]
+            if k == 0:
+                return float(ca[0])
+            return float(ca[k - 1] + (ca[k] - ca[k - 1]) * (level - p[k - 1]) / max(p[k] - p[k - 1], 1e-12))
+
+        mid = crossing(0.5)
+        if mid is None:
             return None
-        k = above[0]
-        if k == 0:
-            return (lo, min(hi, lo + 2 * margin))
-        ca_star = ca[k - 1] + (ca[k] - ca[k - 1]) * (0.5 - p[k - 1]) / max(p[k] - p[k - 1], 1e-12)
-        return (max(lo, ca_star - margin), min(hi, ca_star + margin))
+        q1, q3 = crossing(0.25), crossing(0.75)
+        q3 = hi if q3 is None else q3
+        half = max(tol, 0.5 * (q3 - q1))
+        return (max(lo, mid - half), min(hi, mid + half))
 
     def close(self):
         self.net.close()

@@ -158,8 +158,10 @@ class Search:
     hard_hi: float = 0.0
     lo_ok: bool = False      # lo verified (or assumed) stable
     hi_ok: bool = False      # hi verified broken
+    speculate: bool = True   # run the midpoint alongside unverified ends
     runs: int = 0
     rounds: int = 0
+    updates: int = 0         # lattice-node updates of all runs of the search
     done: bool = False
     outside: str = ""        # "below" / "above" (Ca_cr outside the window) or "failed"
 
@@ -170,12 +172,13 @@ class Search:
 
 def lattice_runner(precision: str = "fp32", log=None, **sim_kw):
     """Default run function of bisect: full simulations, one batch per round.
-    Returns ([(broken, status)], seconds)."""
+    Returns ([(broken, status, node updates)], seconds)."""
     def run(specs):
         if log:
             log(f" round of {len(specs)} runs")
         res, sec = simulate(specs, precision, progress=log, **sim_kw)
-        return [(r.broken, r.status) for r in res], sec
+        return [(r.broken, r.status, r.steps * r.params["nx"] * r.params["ny"] * r.params["nz"])
+                for r in res], sec
     return run
 
 
@@ -183,7 +186,8 @@ def bisect(searches, tol: float = 0.02, run=None, max_rounds: int = 12):
     """Bisection in Ca for every search at once (each round's runs advance as
     one batch).  Per round and search: the unverified bracket ends are
     simulated together with the midpoint (speculatively: the midpoint result
-    is discarded when an end check fails).  A lower end at hard_lo is taken as
+    is discarded when an end check fails; a search with speculate=False runs
+    only its unverified ends until both hold).  A lower end at hard_lo is taken as
     stable without a run (the bottom of the search window).  A failed end
     check moves the bracket outward by twice its width, clipped to the hard
     window: lo broken -> [lo - 2w, lo] (lo now a verified broken end);
@@ -210,7 +214,7 @@ def bisect(searches, tol: float = 0.02, run=None, max_rounds: int = 12):
                 todo.append((s, "lo", s.lo))
             if not s.hi_ok:
                 todo.append((s, "hi", s.hi))
-            if s.hi - s.lo > tol:
+            if s.hi - s.lo > tol and ((s.lo_ok and s.hi_ok) or s.speculate):
                 todo.append((s, "mid", 0.5 * (s.lo + s.hi)))
         if not todo:
             break
@@ -220,8 +224,10 @@ def bisect(searches, tol: float = 0.02, run=None, max_rounds: int = 12):
         total += sec
         rounds += 1
         by_search = {}
-        for (s, what, ca), (broken, status) in zip(todo, outcomes):
+        for (s, what, ca), out in zip(todo, outcomes):
+            broken, status = out[0], out[1]
             s.runs += 1
+            s.updates += out[2] if len(out) > 2 else 0
             by_search.setdefault(id(s), (s, {}))[1][what] = (ca, broken, status)
         for s, res in by_search.values():
             s.rounds += 1

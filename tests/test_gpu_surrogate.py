@@ -125,7 +125,7 @@ def test_trained_network_saves_search_runs(env):
              for q in qs]
     prop = []
     for q in qs:
-        b = sg.propose(q["De"], q["lam"], q["confinement"], lo, hi, margin=tol / 2)
+        b = sg.propose(q["De"], q["lam"], q["confinement"], lo, hi, tol=tol)
         blo, bhi = b if b is not None else (lo, hi)
         prop.append(sweep.Search(q["De"], q["lam"], q["confinement"], 24.0, blo, bhi,
                                  hard_lo=lo, hard_hi=hi))
@@ -141,5 +141,5 @@ def test_trained_network_saves_search_runs(env):
         if t < hi:
             assert a.lo <= t < a.hi and b.lo <= t < b.hi
             assert abs(a.ca_cr - b.ca_cr) <= tol * 1.000001
-    assert runs_prop <= 0.6 * runs_plain
+    assert runs_prop <= 0.8 * runs_plain
     assert r_prop < r_plain

@@ -69,3 +69,25 @@ def test_failed_run_ends_the_search():
     s = search(0.10, 0.26)
     (s,), _, _ = sweep.bisect([s], tol=TOL, run=run)
     assert s.done and s.outside == "failed"
+
+
+def test_no_speculation_checks_the_top_alone():
+    calls = []
+    above = search(0.10, 0.20, De=2.0, lam=0.9, c=0.6, hard=(0.10, 0.20))   # ca_cr = 0.265
+    above.speculate = False
+    (above,), _, rounds = sweep.bisect([above], tol=TOL, run=threshold_runner(calls))
+    assert above.outside == "above" and above.runs == 1 and rounds == 1
+    # a wrong "above" prediction goes on as plain bisection
+    inside = search(0.10, 0.26)
+    inside.speculate = False
+    (inside,), _, _ = sweep.bisect([inside], tol=TOL, run=threshold_runner([]))
+    t = ca_cr(0.5, 0.7, 0.5)
+    assert inside.outside == "" and inside.lo <= t < inside.hi and inside.hi - inside.lo <= TOL * 1.000001
+
+
+def test_updates_are_accumulated():
+    def run(specs):
+        return [(sp.Ca > 0.18, 0, 1000) for sp in specs], 0.0
+    s = search(0.10, 0.26)
+    (s,), _, _ = sweep.bisect([s], tol=TOL, run=run)
+    assert s.updates == 1000 * s.runs
