@@ -289,11 +289,15 @@ __global__ void __launch_bounds__(BX * BY) LBM_COLLIDE_OCC k_collide(StepArgs<T,
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         const int zs = zz - CZ[i];
-        if (CZ[i] == 0 || (zs >= 0 && zs < nz)) {
-          const uint32_t off = (uint32_t)zs * pb + rowb[1 - CY[i]] + colb[1 - CX[i]];
+        const uint32_t off = (uint32_t)zs * pb + rowb[1 - CY[i]] + colb[1 - CX[i]];
+        if (CZ[i] == 0) {
           v[i] = St::load(arr(fs, i, off), 0);
         } else {
-          v[i] = St::load(arr(fs, OPPI[i], own), 0);
+          // uniform choice between the pulled value and the wall's reflection
+          // of the node's own opposite population, made by selects so that
+          // the plane's loads issue back to back
+          const bool in = zs >= 0 && zs < nz;
+          v[i] = St::load(arr(fs, in ? i : OPPI[i], in ? off : own), 0);
         }
       }
     };
@@ -325,18 +329,28 @@ __global__ void __launch_bounds__(BX * BY) LBM_COLLIDE_OCC k_collide(StepArgs<T,
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           const int zs = z - CZ[i];
-          if (CZ[i] == 0 || (zs >= 0 && zs < nz)) {
-            const V4<T> r = ring[zs & 3][lc - CY[i] * HX - CX[i]];
+          if (CZ[i] == 0) {
+            const V4<T> r = ring[z & 3][lc - CY[i] * HX - CX[i]];
             cur[i] = cur[i] - (cur[i] - geq<T>(i, r.x, r.y, r.z, r.w, kS)) * it;
             if (i != 0) cur[i] += (wgt<T>(i) * kS) * (r.x - rx);
           } else {
-            // half-way bounce-back: the population that left x in direction
-            // opp(i) is reflected by the wall it crossed (source: x itself)
+            // Links through z: the pulled value, or (where the link crosses a
+            // wall) the half-way bounce-back of x's own population in
+            // o = opp(i), whose equilibrium has c_o = -c_i and which gains
+            // the moving-wall term -6 w rho c_o.u_wall.  The choice is uniform
+            // and made by selects; the re-reference term vanishes for the
+            // bounce-back (its record is x's own).
+            const bool in = zs >= 0 && zs < nz;
             const int o = OPPI[i];
-            const V4<T> r = ring[z & 3][lc];
+            const V4<T> r = ring[in ? (zs & 3) : (z & 3)][in ? lc - CY[i] * HX - CX[i] : lc];
+            const T sg = in ? T(1) : T(-1);
+            const T cu = sg * (T(CX[i]) * r.y + T(CY[i]) * r.z + T(CZ[i]) * r.w);
+            const T usq = r.y * r.y + r.z * r.z + r.w * r.w;
+            const T ge = (wgt<T>(i) * kS) * r.x * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
             const T uwall = CZ[o] > 0 ? uw : -uw;
-            cur[i] = cur[i] - (cur[i] - geq<T>(o, r.x, r.y, r.z, r.w, kS)) * it
-                     - ((T(6) * kS * wgt<T>(o)) * r.x) * (T(CX[o]) * uwall);
+            const T wall = in ? T(0) : ((T(6) * kS * wgt<T>(o)) * r.x) * (T(CX[o]) * uwall);
+            cur[i] = cur[i] - (cur[i] - ge) * it - wall;
+            cur[i] += (wgt<T>(i) * kS) * (r.x - rx);
           }
           drho += cur[i];
         }
