@@ -185,6 +185,7 @@ __global__ void __launch_bounds__(BX * BY) k_force(StepArgs<T, S> a) {
       }
       const int s0 = rslot(z), sp = rslot(z + 1), sm = rslot(z - 1);
       const T rA = srho[s0][0][lc], rB = srho[s0][1][lc];
+      const T irt = T(1) / (rA + rB);
       T FA0 = -G * rA * sA0, FA1 = -G * rA * sA1, FA2 = -G * rA * sA2;
       T FB0 = -G * rB * sB0, FB1 = -G * rB * sB1, FB2 = -G * rB * sB2;
       if (visc) {
@@ -202,24 +203,24 @@ __global__ void __launch_bounds__(BX * BY) k_force(StepArgs<T, S> a) {
         P0 = ((P0 + dx0) + dy0) + dz0;
         P1 = ((P1 + dx1) + dy1) + dz1;
         P2 = ((P2 + dx2) + dy2) + dz2;
-        const T rt = rA + rB;
-        const T fa = rA / rt, fb = rB / rt;
+        const T fa = rA * irt, fb = rB * irt;
         FA0 = FA0 + fa * P0; FA1 = FA1 + fa * P1; FA2 = FA2 + fa * P2;
         FB0 = FB0 + fb * P0; FB1 = FB1 + fb * P1; FB2 = FB2 + fb * P2;
       }
-      const T den = rA * itA + rB * itB;
-      const T up0 = (jA0 * itA + jB0 * itB) / den;
-      const T up1 = (jA1 * itA + jB1 * itB) / den;
-      const T up2 = (jA2 * itA + jB2 * itB) / den;
+      // one reciprocal per denominator
+      const T iden = T(1) / (rA * itA + rB * itB);
+      const T up0 = (jA0 * itA + jB0 * itB) * iden;
+      const T up1 = (jA1 * itA + jB1 * itB) * iden;
+      const T up2 = (jA2 * itA + jB2 * itB) * iden;
+      const T sA = tA / rA, sB = tB / rB;
       V4<T> ra, rb;
-      ra.x = rA; ra.y = up0 + tA * FA0 / rA; ra.z = up1 + tA * FA1 / rA; ra.w = up2 + tA * FA2 / rA;
-      rb.x = rB; rb.y = up0 + tB * FB0 / rB; rb.z = up1 + tB * FB1 / rB; rb.w = up2 + tB * FB2 / rB;
+      ra.x = rA; ra.y = up0 + sA * FA0; ra.z = up1 + sA * FA1; ra.w = up2 + sA * FA2;
+      rb.x = rB; rb.y = up0 + sB * FB0; rb.z = up1 + sB * FB1; rb.w = up2 + sB * FB2;
       recA[n] = ra;
       recB[n] = rb;
-      const T rt = rA + rB;
-      U[n] = (jA0 + jB0 + T(0.5) * (FA0 + FB0)) / rt;
-      U[N + n] = (jA1 + jB1 + T(0.5) * (FA1 + FB1)) / rt;
-      U[2 * N + n] = (jA2 + jB2 + T(0.5) * (FA2 + FB2)) / rt;
+      U[n] = (jA0 + jB0 + T(0.5) * (FA0 + FB0)) * irt;
+      U[N + n] = (jA1 + jB1 + T(0.5) * (FA1 + FB1)) * irt;
+      U[2 * N + n] = (jA2 + jB2 + T(0.5) * (FA2 + FB2)) * irt;
     }
   }
 }
