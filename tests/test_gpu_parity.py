@@ -166,6 +166,37 @@ def test_repeat_and_checkpoint_bit_identical(lbm, precision):
         s.close()
 
 
+def test_state_of_a_batch_run_round_trips(lbm):
+    """Raw state of one run of a batch restores bit for bit into the same run
+    of a fresh batch; blobs of another box or precision are rejected."""
+    runs = [WL.small_droplet_viscoelastic(),
+            WL.base_params(nx=20, ny=24, nz=18, radius=5.0, tau=(1.0, 0.8),
+                           tau_P=(1.0, 50.0), eta_P=(0.0, 0.05), u_wall=0.01),
+            WL.base_params(nx=17, ny=9, nz=12, radius=3.0, u_wall=0.02)]
+    for prec in ("fp32", "fp16s"):
+        a = lbm.Batch(runs, prec)
+        a.step([30, 17, 25])
+        blob = a.save_state(1)
+        b = lbm.Batch(runs, prec)
+        b.step([3, 0, 0])
+        b.load_state(blob, 1)
+        assert b.observe()[1]["step"] == 17
+        a.step([0, 11, 0])
+        b.step([0, 11, 0])
+        assert np.array_equal(a.export("f", 1), b.export("f", 1)), prec
+        assert np.array_equal(a.export("C", 1), b.export("C", 1)), prec
+        with pytest.raises(lbm.LbmError):
+            b.load_state(blob, 2)          # another box
+        with pytest.raises(lbm.LbmError):
+            b.load_state(blob[:-1], 1)     # wrong size
+        a.close()
+        b.close()
+    c = lbm.Batch(runs, "fp64")
+    with pytest.raises(lbm.LbmError):
+        c.load_state(blob, 1)              # FP16S blob into an FP64 context (size differs)
+    c.close()
+
+
 def test_batch_equals_single_runs(lbm):
     runs = [WL.small_droplet_viscoelastic(),
             WL.base_params(nx=20, ny=24, nz=18, radius=5.0, tau=(1.0, 0.8),
