@@ -144,14 +144,25 @@ int lbm_validate(const lbm_params* p);
 /* ---- single run -------------------------------------------------------
  * Equivalent to the batched calls below with nruns = 1. */
 int lbm_workspace_bytes(const lbm_params* p, size_t* bytes);
-/* Initialise: sphere |x - c|^2 < R^2 holds rho_A = rho_major,
+/* Initialise the set-up of Section 3 (a spherical droplet at mid-gap, shear
+ * started from rest): sphere |x - c|^2 < R^2 holds rho_A = rho_major,
  * rho_B = rho_minor, the rest the reverse; f = w_i rho_s (fluid at rest);
- * C = I.  Enqueued on the stream; returns after enqueueing. */
+ * C = I.  workspace_dev: device memory of at least lbm_workspace_bytes,
+ * owned by the caller until lbm_destroy (else LBM_ENOMEM); hip_stream: the
+ * caller's stream.  Enqueued on the stream; returns after enqueueing. */
 int lbm_init(const lbm_params* p, void* workspace_dev, size_t bytes,
              void* hip_stream, lbm_ctx** out);
-/* Advance nsteps >= 0 steps (asynchronous). */
+/* Advance nsteps >= 0 steps of the coupled scheme (asynchronous): the
+ * lattice-Boltzmann steps of the two components with the Shan-Chen and
+ * polymer forces (Section 2, Eqs. (1) and (3)), then the FENE-P update of C
+ * (Eqs. (2) and (4)), with the moving walls of Section 3.  Faults surface
+ * at the next observe. */
 int lbm_step(lbm_ctx* ctx, int32_t nsteps);
-/* Observables of run 0; synchronises.  Returns LBM_ENAN / LBM_EFENE when the
+/* Observables of run 0 (the quantities the paper reports in Section 3:
+ * deformation and orientation of the droplet, its projected length L_p in
+ * the flow direction as in Fig. 4, and break-up into pieces), reduced in
+ * FP64 with a fixed order; synchronises.  want_components != 0 also labels
+ * the droplet's connected components.  Returns LBM_ENAN / LBM_EFENE when the
  * run's status word is set (out is still filled). */
 int lbm_observe(lbm_ctx* ctx, int32_t want_components, lbm_obs* out);
 /* Copy a field of run 0 to / from a host FP64 buffer of n elements (the
