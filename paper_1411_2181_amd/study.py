@@ -5,6 +5,7 @@ reference.
     python -m paper_1411_2181_amd.study generate DATA.json [--runs 160] [--skip 0] [--near D1.json]
     python -m paper_1411_2181_amd.study search OUT.json --data DATA.json[,DATA2.json] \
         [--queries 16] [--fp64-queries 1]
+    python -m paper_1411_2181_amd.study elongation OUT.json --search SEARCH.json [--queries 4]
 
 Study window (the part of parameter space where the droplet breaks at a
 reachable capillary number): R = 24 (Reynolds number 5-7 at the wall-speed
@@ -268,6 +269,38 @@ def cmd_search(args, log):
     return 0
 
 
+def cmd_elongation(args, log):
+    """Elongation histories L_p(t)/2R of a pre-critical (stable) and a
+    post-critical (breaking) run on each side of a located Ca_cr, the
+    counterpart of the paper's Fig. 4(b), with the number of daughter drops
+    at break-up (two: binary; three or more: multiple necking, Section 3)."""
+    with open(args.search) as fh:
+        found = [r for r in json.load(fh)["search"]["rows"] if r["plain"]["outside"] == ""]
+    specs, tags = [], []
+    for q in found[:args.queries]:
+        lo, hi = q["plain"]["bracket"]
+        for side, ca in (("pre", lo), ("post", hi)):
+            specs.append(sweep.RunSpec(q["R"], q["c"], ca, q["De"], q["lam"]))
+            tags.append(dict(De=q["De"], lam=q["lam"], c=q["c"], R=q["R"], Ca=ca, side=side))
+    res, sec = sweep.simulate(specs, "fp32", t_end=T_END, every=args.every, progress=log)
+    rows = []
+    for t, r in zip(tags, res):
+        tem = r.info["tau_em"]
+        hist = [dict(step=h[0], t_over_tau_em=h[0] / tem, D=h[1], theta=h[2],
+                     Lp_over_2R=h[3] / (2 * t["R"]), pieces=h[4]) for h in r.history]
+        rows.append(dict(t, broken=r.broken, step_break=r.step_break,
+                         daughters=r.history[-1][4] if r.broken else 1,
+                         Lp_max_over_2R=max(h["Lp_over_2R"] for h in hist), tau_em=tem,
+                         history=hist))
+        log(f"{t['side']:4s} Ca={t['Ca']:.3f} De={t['De']:.2f} lam={t['lam']:.2f} c={t['c']:.3f}: "
+            f"{'breaks at %d into %d' % (r.step_break, rows[-1]['daughters']) if r.broken else 'stable'}, "
+            f"max Lp/2R {rows[-1]['Lp_max_over_2R']:.2f}")
+    with open(args.out, "w") as fh:
+        json.dump(dict(seconds=sec, every=args.every, t_end=T_END, rows=rows), fh, indent=1,
+                  default=_plain)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -283,9 +316,15 @@ def main(argv=None):
     s.add_argument("--queries", type=int, default=16)
     s.add_argument("--epochs", type=int, default=3000)
     s.add_argument("--fp64-queries", type=int, default=1)
+    e = sub.add_parser("elongation")
+    e.add_argument("out")
+    e.add_argument("--search", required=True, help="a search output (brackets of located Ca_cr)")
+    e.add_argument("--queries", type=int, default=4)
+    e.add_argument("--every", type=int, default=500)
     args = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
-    return cmd_generate(args, log) if args.cmd == "generate" else cmd_search(args, log)
+    cmd = {"generate": cmd_generate, "search": cmd_search, "elongation": cmd_elongation}
+    return cmd[args.cmd](args, log)
 
 
 if __name__ == "__main__":
