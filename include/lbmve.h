@@ -121,6 +121,10 @@ typedef struct {
   int32_t n_components;  /* droplet pieces >= 1% of the initial droplet
                             volume (6-connected, periodic x, y); -1 if not
                             requested                                         */
+  int32_t piece_nodes[4];/* node counts of the largest such pieces in
+                            descending order (0 past n_components or if not
+                            requested): the daughter-size spread of a
+                            break-up (Section 3)                              */
   int32_t status;        /* LBM_OK, LBM_ENAN or LBM_EFENE for this run       */
 } lbm_obs;
 

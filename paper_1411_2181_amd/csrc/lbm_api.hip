@@ -58,7 +58,7 @@ bool coexistence(double G, double rho_tot, double* lo, double* hi) {
 }
 
 struct Layout {
-  size_t f[2], rho[2], j[2], C[2], recA, recB, u, labels, counts, status, ncomp, gstep,
+  size_t f[2], rho[2], j[2], C[2], recA, recB, u, labels, counts, status, ncomp, pieces, gstep,
       runs, tiles, partials, obs, rc, rinit, total;
   int64_t tiles_cap;
 };
@@ -97,6 +97,7 @@ Layout make_layout(const lbm_params* p, int32_t nruns) {
   L.counts = take((size_t)nodes * 4);
   L.status = take((size_t)nruns * 4);
   L.ncomp = take((size_t)nruns * 4);
+  L.pieces = take((size_t)nruns * lbm::MAX_PIECES * 4);
   L.gstep = take(4);
   L.runs = take((size_t)nruns * sizeof(RunDev));
   L.tiles_cap = max_tiles(p, nruns);
@@ -175,6 +176,7 @@ lbm::AuxArgs<T, S> aux_args(const lbm_ctx* c, int use_parity) {
   a.labels = c->at<int32_t>(c->L.labels);
   a.counts = c->at<int32_t>(c->L.counts);
   a.ncomp = c->at<int32_t>(c->L.ncomp);
+  a.pieces = c->at<int32_t>(c->L.pieces);
   a.radius_centre = c->at<double>(c->L.rc);
   a.rho_init = c->at<double>(c->L.rinit);
   return a;
@@ -449,6 +451,7 @@ void finish_obs(const lbm_ctx* c, int r, const double* o, lbm_obs* out) {
   out->umax = std::sqrt(o[lbm::OB_U2MAX]);
   out->trC_max = o[lbm::OB_TRCMAX];
   out->n_components = -1;
+  for (int i = 0; i < 4; ++i) out->piece_nodes[i] = 0;
 }
 
 }  // namespace
@@ -649,15 +652,24 @@ int lbm_batch_observe(lbm_ctx* c, int32_t want_cc, lbm_obs* out) {
   HIPCHK(hipGetLastError());
   std::vector<double> o((size_t)c->nruns * lbm::NOBS);
   std::vector<uint32_t> st(c->nruns);
-  std::vector<int32_t> nc(c->nruns);
+  std::vector<int32_t> nc(c->nruns), pc((size_t)c->nruns * lbm::MAX_PIECES);
   HIPCHK(hipMemcpyAsync(o.data(), c->at<double>(c->L.obs), o.size() * 8, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipMemcpyAsync(st.data(), c->at<uint32_t>(c->L.status), st.size() * 4, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipMemcpyAsync(nc.data(), c->at<int32_t>(c->L.ncomp), nc.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(pc.data(), c->at<int32_t>(c->L.pieces), pc.size() * 4, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   int first = LBM_OK;
   for (int r = 0; r < c->nruns; ++r) {
     finish_obs(c, r, o.data() + (size_t)r * lbm::NOBS, out + r);
-    if (want_cc) out[r].n_components = nc[r];
+    if (want_cc) {
+      out[r].n_components = nc[r];
+      // sizes of the largest pieces, in descending order
+      const int k = std::min<int>(nc[r], lbm::MAX_PIECES);
+      std::vector<int32_t> sz(pc.begin() + (size_t)r * lbm::MAX_PIECES,
+                              pc.begin() + (size_t)r * lbm::MAX_PIECES + k);
+      std::sort(sz.begin(), sz.end(), [](int32_t p, int32_t q) { return p > q; });
+      for (int i = 0; i < 4 && i < k; ++i) out[r].piece_nodes[i] = sz[i];
+    }
     int s = LBM_OK;
     if ((st[r] & lbm::ST_NAN) || o[(size_t)r * lbm::NOBS + lbm::OB_NONFINITE] > 0) s = LBM_ENAN;
     else if (st[r] & lbm::ST_FENE) s = LBM_EFENE;

@@ -284,10 +284,13 @@ __global__ void k_cc_count(AuxArgs<T, S> a) {
   node_range(R.n, beg, end);
   const int32_t* L = a.labels + R.off;
   const int32_t* cnt = a.counts + R.off;
-  int mine = 0;
+  // each counted piece (a root of at least min_cc nodes) takes a slot and
+  // records its size there; the host orders the sizes
   for (int64_t n = beg + threadIdx.x; n < end; n += blockDim.x)
-    if (L[n] == (int32_t)n && cnt[n] >= R.min_cc) ++mine;
-  if (mine) atomicAdd(a.ncomp + r, mine);
+    if (L[n] == (int32_t)n && cnt[n] >= R.min_cc) {
+      const int slot = atomicAdd(a.ncomp + r, 1);
+      if (slot < MAX_PIECES) a.pieces[r * MAX_PIECES + slot] = cnt[n];
+    }
 }
 
 // ---- small helpers ----------------------------------------------------------------

@@ -28,6 +28,8 @@ enum ObsSlot {
 constexpr int AUX_BLOCKS = 128;
 constexpr int AUX_THREADS = 256;
 
+constexpr int MAX_PIECES = 8;   // pieces whose sizes are kept per run
+
 template <typename T, typename S>
 struct AuxArgs {
   Pools<T, S> P;
@@ -38,7 +40,8 @@ struct AuxArgs {
   double* obs;             // [nruns][NOBS]
   int32_t* labels;         // per node (component labelling)
   int32_t* counts;         // per node
-  int32_t* ncomp;          // per run
+  int32_t* ncomp;          // per run: pieces counted
+  int32_t* pieces;         // [nruns][MAX_PIECES]: node counts of counted pieces, unordered
   const double* radius_centre;  // [nruns][4]: R, cx, cy, cz  (init only)
   const double* rho_init;       // [nruns][2]: rho_major, rho_minor (init only)
 };

@@ -58,6 +58,7 @@ class LbmObs(ctypes.Structure):
         ("umax", ctypes.c_double),
         ("trC_max", ctypes.c_double),
         ("n_components", ctypes.c_int32),
+        ("piece_nodes", ctypes.c_int32 * 4),
         ("status", ctypes.c_int32),
     ]
 
@@ -67,7 +68,7 @@ class LbmObs(ctypes.Structure):
                     inertia=tuple(self.inertia), D=self.D,
                     theta_deg=self.theta_deg, Lp=self.Lp, umax=self.umax,
                     trC_max=self.trC_max, n_components=int(self.n_components),
-                    status=int(self.status))
+                    piece_nodes=[int(v) for v in self.piece_nodes], status=int(self.status))
 
 
 class LbmLaunch(ctypes.Structure):

@@ -8,14 +8,17 @@ reference.
     python -m paper_1411_2181_amd.study elongation OUT.json --search SEARCH.json [--queries 4]
 
 Study window (the part of parameter space where the droplet breaks at a
-reachable capillary number): R = 24 (Reynolds number 5-7 at the wall-speed
-cap, where break-up sets in at Ca ~ 0.2), confinement c ~ U[0.45, 0.6],
-viscosity ratio lambda ~ U[0.6, 0.9] (below ~0.6 a viscoelastic droplet's
-solvent tau drops under ~0.85 and runs at the wall-speed cap lose
-stability), De in {0, 0.5, 1, 2}, L^2 in {100, 400}, polymer fraction in
-{0.2, 0.4}, droplet viscoelastic.  Ca ~ U[CA_LO, Ca_max], Ca_max the value at
-the U_w = 0.19 cap.  Each run lasts up to T_END steps and is checked for
-break-up every EVERY steps (a run stops once it breaks).
+reachable capillary number and keeps its volume): R = 24 (Reynolds number
+5-7 at the wall-speed cap, where break-up sets in at Ca ~ 0.2), confinement
+c ~ U[0.45, 0.65], De in {0, 0.5, 1, 2}, L^2 in {100, 400}, polymer fraction
+f in {0.2, 0.4}, droplet viscoelastic.  The droplet's solvent is held at
+tau_A = TAU_DROP next to the tau = 1.5 matrix: with the velocity-shift
+forcing a droplet whose tau is lower takes up matrix component and swells
+(by 36-65 % over 16000 steps at tau_A = 0.86-1.1), at 1.3 it keeps its
+volume.  The viscosity ratio is therefore lambda = LAM_N / (1 - f)
+(LAM_N = 0.8 for a Newtonian droplet).  Ca ~ U[CA_LO, Ca_max], Ca_max the
+value at the U_w = 0.19 cap.  Each run lasts up to T_END steps and is checked
+for break-up every EVERY steps (a run stops once it breaks).
 
 Training data: a first batch from the window sampler, then (``--near``) a
 batch placed where the network trained on the first one is uncertain.
@@ -42,20 +45,29 @@ import workloads as WL
 from . import sweep
 from .surrogate import Surrogate
 
-CA_LO = 0.10
+CA_LO = 0.12
+LAM_N = 0.8          # Newtonian droplet: tau_A = 0.5 + 3 LAM_N eta_M = 1.3 at tau_M = 1.5
 T_END = 16000
 EVERY = 2000
 TOL = 0.02
+
+
+def window_lambda(De: float, fraction: float):
+    """Viscosity ratio and polymer fraction that keep the droplet's solvent
+    at tau_A = 1.3: lambda = LAM_N/(1 - f) with polymer, LAM_N without."""
+    if De <= 0.0:
+        return LAM_N, 0.0
+    return LAM_N / (1.0 - fraction), fraction
 
 
 def sample_specs(n: int, base_seed: int = 98765):
     specs = []
     for k in range(n):
         d = WL.surrogate_window_sampler(k, base_seed)
-        hi = sweep.ca_max(d["R"], d["confinement"], d["lam"], d["De"], d["polymer_fraction"])
+        lam, f = window_lambda(d["De"], d["polymer_fraction"])
+        hi = sweep.ca_max(d["R"], d["confinement"], lam, d["De"], f)
         Ca = CA_LO + d["u"] * (hi - CA_LO)
-        specs.append(sweep.RunSpec(d["R"], d["confinement"], Ca, d["De"], d["lam"], d["L2"],
-                                   d["polymer_fraction"]))
+        specs.append(sweep.RunSpec(d["R"], d["confinement"], Ca, d["De"], lam, d["L2"], f))
     return specs
 
 
@@ -80,11 +92,15 @@ def generate(specs, chunk: int = 20, log=print, save=None):
 
 
 def query_searches(n: int):
-    return [dict(De=q["De"], lam=q["lam"], c=q["confinement"], R=q["R"]) for q in WL.query_window(n)]
+    out = []
+    for q in WL.query_window(n):
+        lam, f = window_lambda(q["De"], q["polymer_fraction"])
+        out.append(dict(De=q["De"], lam=lam, c=q["confinement"], R=q["R"], fraction=f))
+    return out
 
 
 def window(q):
-    return CA_LO, sweep.ca_max(q["R"], q["c"], q["lam"], q["De"])
+    return CA_LO, sweep.ca_max(q["R"], q["c"], q["lam"], q["De"], q["fraction"])
 
 
 def single_runner(precision: str, log=None):
@@ -273,7 +289,9 @@ def cmd_elongation(args, log):
     """Elongation histories L_p(t)/2R of a pre-critical (stable) and a
     post-critical (breaking) run on each side of a located Ca_cr, the
     counterpart of the paper's Fig. 4(b), with the number of daughter drops
-    at break-up (two: binary; three or more: multiple necking, Section 3)."""
+    at break-up (two: binary; three or more: multiple necking, Section 3) and
+    their sizes (the spread, (largest - smallest) / mean, measures how far
+    from monodisperse the daughters are)."""
     with open(args.search) as fh:
         found = [r for r in json.load(fh)["search"]["rows"] if r["plain"]["outside"] == ""]
     specs, tags = [], []
@@ -288,12 +306,15 @@ def cmd_elongation(args, log):
         tem = r.info["tau_em"]
         hist = [dict(step=h[0], t_over_tau_em=h[0] / tem, D=h[1], theta=h[2],
                      Lp_over_2R=h[3] / (2 * t["R"]), pieces=h[4]) for h in r.history]
+        sizes = r.pieces
+        spread = (max(sizes) - min(sizes)) / (sum(sizes) / len(sizes)) if sizes else None
         rows.append(dict(t, broken=r.broken, step_break=r.step_break,
                          daughters=r.history[-1][4] if r.broken else 1,
+                         daughter_nodes=sizes, daughter_spread=spread,
                          Lp_max_over_2R=max(h["Lp_over_2R"] for h in hist), tau_em=tem,
                          history=hist))
         log(f"{t['side']:4s} Ca={t['Ca']:.3f} De={t['De']:.2f} lam={t['lam']:.2f} c={t['c']:.3f}: "
-            f"{'breaks at %d into %d' % (r.step_break, rows[-1]['daughters']) if r.broken else 'stable'}, "
+            f"{'breaks at %d into %d %s' % (r.step_break, rows[-1]['daughters'], sizes) if r.broken else 'stable'}, "
             f"max Lp/2R {rows[-1]['Lp_max_over_2R']:.2f}")
     with open(args.out, "w") as fh:
         json.dump(dict(seconds=sec, every=args.every, t_end=T_END, rows=rows), fh, indent=1,

@@ -57,6 +57,7 @@ class RunResult:
     theta: float = float("nan")
     Lp_max: float = 0.0
     status: int = 0
+    pieces: list = field(default_factory=list)   # node counts of the pieces at break-up
     history: list = field(default_factory=list)
 
 
@@ -129,6 +130,7 @@ def simulate(specs, precision: str = "fp32", t_end: int | None = None, every: in
             elif o["n_components"] >= 2:
                 r.broken = True
                 r.step_break = o["step"]
+                r.pieces = [v for v in o["piece_nodes"] if v > 0]
                 remaining[k] = 0
         if progress:
             progress(f"  step {max(r.steps for r in results)}: "

@@ -266,10 +266,11 @@ def test_component_count_matches_oracle(lbm):
     f = np.stack([d3q19.W[:, None, None, None] * rA, d3q19.W[:, None, None, None] * rB])
     s = lbm.Solver(d, "fp64")
     s.import_("f", f)
-    got = s.observe(components=True)["n_components"]
+    o = s.observe(components=True)
     sizes = component_sizes(m)
-    want = sum(1 for v in sizes if v >= 22)
-    assert got == want == 3
+    big = sorted((v for v in sizes if v >= 22), reverse=True)
+    assert o["n_components"] == len(big) == 3
+    assert o["piece_nodes"] == big + [0] * (4 - len(big))
     s.close()
 
 

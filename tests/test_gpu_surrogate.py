@@ -97,19 +97,20 @@ def test_trained_network_saves_search_runs(env):
     from paper_1411_2181_amd.surrogate import Surrogate
 
     def ca_cr(De, lam, c):
-        return 0.17 + 0.02 * De + 0.1 * (lam - 0.75) + 0.2 * (c - 0.5)
+        return 0.16 + 0.02 * De + 0.05 * (lam - 1.0) + 0.2 * (c - 0.5)
 
     def run(specs):
         return [(sp.Ca > ca_cr(sp.De, sp.lam, sp.c), 0) for sp in specs], 0.0
 
+    # inputs as in the study window: lambda = 0.8 / (1 - f) with polymer
     rng = np.random.default_rng(11)
     n = 600
     De = rng.choice([0.0, 0.5, 1.0, 2.0], size=n)
-    lam = rng.uniform(0.6, 0.9, size=n)
-    c = rng.uniform(0.45, 0.6, size=n)
+    fr = np.where(De > 0, rng.choice([0.2, 0.4], size=n), 0.0)
+    lam = 0.8 / (1.0 - fr)
+    c = rng.uniform(0.45, 0.65, size=n)
     Ca = rng.uniform(0.10, 0.26, size=n)
     L2 = rng.choice([100.0, 400.0], size=n)
-    fr = rng.choice([0.2, 0.4], size=n)
     X = np.stack([Ca, De, lam, c, L2, fr], axis=1)
     cr = ca_cr(De, lam, c)
     broken = (Ca > cr).astype(float)
@@ -121,6 +122,8 @@ def test_trained_network_saves_search_runs(env):
 
     tol, lo, hi = 0.02, 0.10, 0.26
     qs = WL.query_window(16)
+    for q in qs:
+        q["lam"] = 0.8 / (1.0 - q["polymer_fraction"])
     plain = [sweep.Search(q["De"], q["lam"], q["confinement"], 24.0, lo, hi, hard_lo=lo, hard_hi=hi)
              for q in qs]
     prop = []
@@ -128,7 +131,7 @@ def test_trained_network_saves_search_runs(env):
         b = sg.propose(q["De"], q["lam"], q["confinement"], lo, hi, tol=tol)
         blo, bhi = b if b is not None else (lo, hi)
         prop.append(sweep.Search(q["De"], q["lam"], q["confinement"], 24.0, blo, bhi,
-                                 hard_lo=lo, hard_hi=hi))
+                                 hard_lo=lo, hard_hi=hi, speculate=b is not None))
     sg.close()
     plain, _, r_plain = sweep.bisect(plain, tol=tol, run=run)
     prop, _, r_prop = sweep.bisect(prop, tol=tol, run=run)

@@ -152,14 +152,14 @@ def query_triples(n: int = 32, seed: int = 4242) -> list[dict]:
 
 def surrogate_window_sampler(k: int, base_seed: int = 98765) -> dict:
     """Training-run sampler of the Ca_cr study window: R = 24; confinement
-    c ~ U[0.45, 0.6]; lambda ~ U[0.6, 0.9]; De in {0, 0.5, 1, 2}; L^2 in
-    {100, 400}; polymer fraction in {0.2, 0.4}; droplet phase viscoelastic.
-    ``u`` ~ U[0, 1) places Ca inside the run's reachable range (the caller
-    maps it, since that range depends on the lattice mapping)."""
+    c ~ U[0.45, 0.65]; De in {0, 0.5, 1, 2}; L^2 in {100, 400}; polymer
+    fraction in {0.2, 0.4} (unused when De = 0); droplet phase viscoelastic.
+    ``u`` ~ U[0, 1) places Ca inside the run's reachable range, and the
+    viscosity ratio follows from the window's solvent rule (the caller maps
+    both, since they depend on the lattice mapping)."""
     rng = np.random.default_rng(base_seed + k)
     return dict(k=k, seed=base_seed + k, R=24.0,
-                confinement=float(rng.uniform(0.45, 0.6)),
-                lam=float(rng.uniform(0.6, 0.9)),
+                confinement=float(rng.uniform(0.45, 0.65)),
                 De=float(rng.choice([0.0, 0.5, 1.0, 2.0])),
                 L2=float(rng.choice([100.0, 400.0])),
                 polymer_fraction=float(rng.choice([0.2, 0.4])),
@@ -167,12 +167,11 @@ def surrogate_window_sampler(k: int, base_seed: int = 98765) -> dict:
 
 
 def query_window(n: int = 16, seed: int = 4242) -> list[dict]:
-    """(De, lambda, c) query triples inside the study window (L^2 = 100,
-    polymer fraction 0.4, R = 24)."""
+    """(De, c) query pairs inside the study window (L^2 = 100, polymer
+    fraction 0.4, R = 24; the viscosity ratio follows from the fraction)."""
     rng = np.random.default_rng(seed)
-    return [dict(De=float(rng.uniform(0.0, 2.0)), lam=float(rng.uniform(0.6, 0.9)),
-                 confinement=float(rng.uniform(0.45, 0.6)), L2=100.0,
-                 polymer_fraction=0.4, R=24.0) for _ in range(n)]
+    return [dict(De=float(rng.uniform(0.25, 2.0)), confinement=float(rng.uniform(0.45, 0.65)),
+                 L2=100.0, polymer_fraction=0.4, R=24.0) for _ in range(n)]
 
 
 # ----------------------------------------------------------------------------
