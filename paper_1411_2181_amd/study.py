@@ -4,7 +4,7 @@ reference.
 
     python -m paper_1411_2181_amd.study generate DATA.json [--runs 160] [--skip 0] [--near D1.json]
     python -m paper_1411_2181_amd.study search OUT.json --data DATA.json[,DATA2.json] \
-        [--queries 16] [--fp64-queries 1]
+        [--queries 16] [--fp64-queries 1] [--precision fp32|fp16s]
     python -m paper_1411_2181_amd.study elongation OUT.json --search SEARCH.json [--queries 4]
 
 Study window (the part of parameter space where the droplet breaks at a
@@ -28,7 +28,7 @@ Searches: tolerance 0.02 (Ca_cr located within +-0.01), window
 window; the surrogate's search starts from the network's bracket (centred
 where its break-up probability crosses 1/2, at least +-0.02 wide) and falls
 back outward when a bracket end fails (sweep.bisect).  Both advance every query's runs of a round
-as one batch (FP32).  The plain FP64 one-run-at-a-time variant is timed on
+as one batch (FP32 or FP16S storage).  The plain FP64 one-run-at-a-time variant is timed on
 ``--fp64-queries`` triples.
 """
 from __future__ import annotations
@@ -95,7 +95,7 @@ def query_searches(n: int):
     out = []
     for q in WL.query_window(n):
         lam, f = window_lambda(q["De"], q["polymer_fraction"])
-        out.append(dict(De=q["De"], lam=lam, c=q["confinement"], R=q["R"], fraction=f))
+        out.append(dict(De=q["De"], lam=lam, c=q["confinement"], R=q["R"], L2=q["L2"], fraction=f))
     return out
 
 
@@ -210,13 +210,15 @@ def cmd_search(args, log):
         out = []
         for q in qs:
             lo, hi = window(q)
-            out.append(sweep.Search(q["De"], q["lam"], q["c"], q["R"], lo, hi, hard_lo=lo, hard_hi=hi))
+            out.append(sweep.Search(q["De"], q["lam"], q["c"], q["R"], lo, hi, hard_lo=lo, hard_hi=hi,
+                                    L2=q["L2"], fraction=q["fraction"]))
         return out
 
-    # plain bisection, batched FP32
-    plain, t_plain, r_plain = sweep.bisect(plain_searches(), tol=TOL,
-                                           run=sweep.lattice_runner("fp32", log=log, t_end=T_END, every=EVERY))
-    log(f"plain bisection: {t_plain:.1f} s, {r_plain} rounds, {sum(s.runs for s in plain)} runs")
+    prec = args.precision
+    # plain bisection, batched
+    run_plain = sweep.lattice_runner(prec, log=log, t_end=T_END, every=EVERY)
+    plain, t_plain, r_plain = sweep.bisect(plain_searches(), tol=TOL, run=run_plain)
+    log(f"plain bisection ({prec}): {t_plain:.1f} s, {r_plain} rounds, {sum(s.runs for s in plain)} runs")
 
     # surrogate-proposed brackets, batched FP32
     prop, proposals = [], []
@@ -228,10 +230,10 @@ def cmd_search(args, log):
         # if it breaks after all, the search goes on as plain bisection
         blo, bhi = b if b is not None else (lo, hi)
         prop.append(sweep.Search(q["De"], q["lam"], q["c"], q["R"], blo, bhi, hard_lo=lo, hard_hi=hi,
-                                 speculate=b is not None))
-    prop, t_sg, r_sg = sweep.bisect(prop, tol=TOL,
-                                    run=sweep.lattice_runner("fp32", log=log, t_end=T_END, every=EVERY))
-    log(f"surrogate-bracketed: {t_sg:.1f} s, {r_sg} rounds, {sum(s.runs for s in prop)} runs")
+                                 L2=q["L2"], fraction=q["fraction"], speculate=b is not None))
+    run_sg = sweep.lattice_runner(prec, log=log, t_end=T_END, every=EVERY)
+    prop, t_sg, r_sg = sweep.bisect(prop, tol=TOL, run=run_sg)
+    log(f"surrogate-bracketed ({prec}): {t_sg:.1f} s, {r_sg} rounds, {sum(s.runs for s in prop)} runs")
 
     rows_q, agree, comparable = [], 0, 0
     for q, a, b, pb in zip(qs, plain, prop, proposals):
@@ -244,13 +246,16 @@ def cmd_search(args, log):
             comparable += 1
             agree += (a.outside != "" or abs(a.ca_cr - b.ca_cr) <= TOL)
     # sweeps per hour at saturation: with many queries in flight the GPU is
-    # full and time goes as lattice updates (batched FP32 rate of the data
-    # generation), not as rounds
-    rate = data["updates"] / data["seconds"]
+    # full and time goes as lattice updates, not as rounds.  The saturated
+    # rate is that of the largest batch either search ran (the plain search's
+    # first round: two runs per query).
+    big = max(run_plain.rounds + run_sg.rounds)
+    rate = big[1] / big[2]
     upd_plain = sum(s.updates for s in plain)
     upd_sg = sum(s.updates for s in prop)
     report["search"] = dict(
-        queries=len(qs), tol=TOL, t_end=T_END,
+        queries=len(qs), tol=TOL, t_end=T_END, precision=prec,
+        saturated_batch=dict(runs=big[0], updates=big[1], seconds=big[2]),
         plain=dict(seconds=t_plain, rounds=r_plain, runs=sum(s.runs for s in plain),
                    updates=upd_plain, sweeps_per_hour=len(qs) / t_plain * 3600,
                    sweeps_per_hour_saturated=len(qs) / (upd_plain / rate) * 3600),
@@ -258,14 +263,15 @@ def cmd_search(args, log):
                        updates=upd_sg, sweeps_per_hour=len(qs) / t_sg * 3600,
                        sweeps_per_hour_saturated=len(qs) / (upd_sg / rate) * 3600,
                        first_round_hits=sum(1 for s in prop if s.rounds == 1 and s.outside == "")),
-        batched_fp32_rate_mlups=rate / 1e6,
+        batched_rate_mlups=rate / 1e6,
         same_outcome=comparable, agree_within_tol=agree, rows=rows_q)
 
     # plain FP64, one run at a time, on the first triples
     t64, n64, runs64 = 0.0, 0, 0
     for q in qs[:args.fp64_queries]:
         lo, hi = window(q)
-        s64 = [sweep.Search(q["De"], q["lam"], q["c"], q["R"], lo, hi, hard_lo=lo, hard_hi=hi)]
+        s64 = [sweep.Search(q["De"], q["lam"], q["c"], q["R"], lo, hi, hard_lo=lo, hard_hi=hi,
+                            L2=q["L2"], fraction=q["fraction"])]
         s64, t, _ = sweep.bisect(s64, tol=TOL, run=single_runner("fp64", log))
         t64 += t
         n64 += 1
@@ -298,7 +304,8 @@ def cmd_elongation(args, log):
     for q in found[:args.queries]:
         lo, hi = q["plain"]["bracket"]
         for side, ca in (("pre", lo), ("post", hi)):
-            specs.append(sweep.RunSpec(q["R"], q["c"], ca, q["De"], q["lam"]))
+            specs.append(sweep.RunSpec(q["R"], q["c"], ca, q["De"], q["lam"], q.get("L2", 100.0),
+                                       q["fraction"]))
             tags.append(dict(De=q["De"], lam=q["lam"], c=q["c"], R=q["R"], Ca=ca, side=side))
     res, sec = sweep.simulate(specs, "fp32", t_end=T_END, every=args.every, progress=log)
     rows = []
@@ -337,6 +344,8 @@ def main(argv=None):
     s.add_argument("--queries", type=int, default=16)
     s.add_argument("--epochs", type=int, default=3000)
     s.add_argument("--fp64-queries", type=int, default=1)
+    s.add_argument("--precision", default="fp32", choices=["fp32", "fp16s"],
+                   help="storage of the batched searches")
     e = sub.add_parser("elongation")
     e.add_argument("out")
     e.add_argument("--search", required=True, help="a search output (brackets of located Ca_cr)")

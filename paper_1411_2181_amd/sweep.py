@@ -158,6 +158,8 @@ class Search:
     hi: float
     hard_lo: float = 0.0
     hard_hi: float = 0.0
+    L2: float = 100.0
+    fraction: float = 0.4
     lo_ok: bool = False      # lo verified (or assumed) stable
     hi_ok: bool = False      # hi verified broken
     speculate: bool = True   # run the midpoint alongside unverified ends
@@ -174,13 +176,17 @@ class Search:
 
 def lattice_runner(precision: str = "fp32", log=None, **sim_kw):
     """Default run function of bisect: full simulations, one batch per round.
-    Returns ([(broken, status, node updates)], seconds)."""
+    Returns ([(broken, status, node updates)], seconds).  ``run.rounds`` lists
+    (runs, node updates, seconds) per round."""
     def run(specs):
         if log:
             log(f" round of {len(specs)} runs")
         res, sec = simulate(specs, precision, progress=log, **sim_kw)
-        return [(r.broken, r.status, r.steps * r.params["nx"] * r.params["ny"] * r.params["nz"])
-                for r in res], sec
+        out = [(r.broken, r.status, r.steps * r.params["nx"] * r.params["ny"] * r.params["nz"])
+               for r in res]
+        run.rounds.append((len(specs), sum(o[2] for o in out), sec))
+        return out, sec
+    run.rounds = []
     return run
 
 
@@ -221,7 +227,7 @@ def bisect(searches, tol: float = 0.02, run=None, max_rounds: int = 12):
         if not todo:
             break
         for s, _, ca in todo:
-            specs.append(RunSpec(s.R, s.c, ca, s.De, s.lam))
+            specs.append(RunSpec(s.R, s.c, ca, s.De, s.lam, s.L2, s.fraction))
         outcomes, sec = run(specs)
         total += sec
         rounds += 1

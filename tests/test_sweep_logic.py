@@ -91,3 +91,14 @@ def test_updates_are_accumulated():
     s = search(0.10, 0.26)
     (s,), _, _ = sweep.bisect([s], tol=TOL, run=run)
     assert s.updates == 1000 * s.runs
+
+
+def test_runs_carry_the_search_polymer_parameters():
+    seen = []
+
+    def run(specs):
+        seen.extend((sp.L2, sp.fraction) for sp in specs)
+        return [(sp.Ca > 0.18, 0) for sp in specs], 0.0
+    s = sweep.Search(1.0, 4 / 3, 0.5, 24.0, 0.10, 0.26, hard_lo=0.10, hard_hi=0.26, L2=400.0, fraction=0.2)
+    sweep.bisect([s], tol=TOL, run=run)
+    assert seen and all(v == (400.0, 0.2) for v in seen)
