@@ -102,9 +102,14 @@ __global__ void __launch_bounds__(BX * BY) k_force(StepArgs<T, S> a) {
     V4<T>* __restrict__ recA = a.P.recA + R.off;
     V4<T>* __restrict__ recB = a.P.recB + R.off;
     T* __restrict__ U = a.P.u + 3 * R.off;
+    // run parameters in registers: a load of them inside the z-march would
+    // wait for every load in flight (the prefetched planes) as well
     const T G = T(R.G);
     const T tA = T(R.tau[0]), tB = T(R.tau[1]);
     const T itA = T(R.inv_tau[0]), itB = T(R.inv_tau[1]);
+    const int vph = R.visc;
+    const T chi_lo = T(R.chi_lo), ichr = T(R.inv_chi_range), eP = T(R.etaP_over_tauP);
+    const double L2 = R.L2;
     T raw[KP][8];
     auto load_raw = [&](int zp) {
       const int zc = zp < 0 ? 0 : (zp >= nz ? nz - 1 : zp);
@@ -138,12 +143,12 @@ __global__ void __launch_bounds__(BX * BY) k_force(StepArgs<T, S> a) {
           srho[sl][0][k] = rA;
           srho[sl][1][k] = rB;
           if (visc) {
-            const T rp = R.visc == 0 ? rA : rB;
-            T chi = (rp / (rA + rB) - T(R.chi_lo)) * T(R.inv_chi_range);
+            const T rp = vph == 0 ? rA : rB;
+            T chi = (rp / (rA + rB) - chi_lo) * ichr;
             chi = chi < T(0) ? T(0) : (chi > T(1) ? T(1) : chi);
             const double tr = (double)raw[kk][2] + (double)raw[kk][3] + (double)raw[kk][4];
-            const T fP = (T)((R.L2 - 3.0) / (R.L2 - tr));
-            const T coef = chi * T(R.etaP_over_tauP);
+            const T fP = (T)((L2 - 3.0) / (L2 - tr));
+            const T coef = chi * eP;
 #pragma unroll
             for (int c = 0; c < 6; ++c)
               sT[sl][c][k] = coef * (fP * raw[kk][2 + c] - (c < 3 ? T(1) : T(0)));
@@ -159,18 +164,27 @@ __global__ void __launch_bounds__(BX * BY) k_force(StepArgs<T, S> a) {
     store_raw(tl.z0);
     load_raw(tl.z0 + 1);
     const int lc = (ty + 1) * HX + (tx + 1);
-    for (int z = tl.z0; z < zend; ++z) {
+    // momenta of the thread's node, one plane ahead (inactive threads of a
+    // ragged tile read a valid node and discard it); the two register sets
+    // alternate roles (the march is unrolled by two planes), so no copy
+    // waits for loads in flight
+    auto load_j = [&](int zz, T (&v)[6]) {
+      const int64_t m = nid(active ? x : 0, active ? y : 0, zz, nx, ny);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[c] = J[c * N + m];
+    };
+    auto plane = [&](int z, const T (&jc)[6], T (&jn)[6]) {
       if (RS == 3) __syncthreads();   // plane z-2's slot is free (plane z-1 done)
       store_raw(z + 1);
-      if (z + 2 <= zend) load_raw(z + 2);
+      // the loads of plane z+2 and of the momenta of plane z+1 stay in
+      // flight while plane z is computed; past the tile's end they re-read
+      // its last planes (in bounds, unused)
+      load_raw(min(z + 2, zend));
+      load_j(min(z + 1, zend - 1), jn);
       const int64_t n = nid(active ? x : 0, active ? y : 0, z, nx, ny);
-      T jA0 = 0, jA1 = 0, jA2 = 0, jB0 = 0, jB1 = 0, jB2 = 0;
-      if (active) {
-        jA0 = J[n]; jA1 = J[N + n]; jA2 = J[2 * N + n];
-        jB0 = J[3 * N + n]; jB1 = J[4 * N + n]; jB2 = J[5 * N + n];
-      }
       __syncthreads();
-      if (!active) continue;
+      if (!active) return;
+      const T jA0 = jc[0], jA1 = jc[1], jA2 = jc[2], jB0 = jc[3], jB1 = jc[4], jB2 = jc[5];
       // Shan-Chen: F_A = -G rho_A sum_i 3 w_i rho_B(x+c_i) c_i (and A<->B)
       T sA0 = 0, sA1 = 0, sA2 = 0, sB0 = 0, sB1 = 0, sB2 = 0;
 #pragma unroll
@@ -221,6 +235,12 @@ __global__ void __launch_bounds__(BX * BY) k_force(StepArgs<T, S> a) {
       U[n] = (jA0 + jB0 + T(0.5) * (FA0 + FB0)) * irt;
       U[N + n] = (jA1 + jB1 + T(0.5) * (FA1 + FB1)) * irt;
       U[2 * N + n] = (jA2 + jB2 + T(0.5) * (FA2 + FB2)) * irt;
+    };
+    T ja[6], jb[6];
+    load_j(tl.z0, ja);
+    for (int z = tl.z0; z < zend; z += 2) {
+      plane(z, ja, jb);
+      if (z + 1 < zend) plane(z + 1, jb, ja);
     }
   }
 }
@@ -234,6 +254,7 @@ __global__ void __launch_bounds__(BX * BY) k_force(StepArgs<T, S> a) {
 template <typename T, typename S, int BX, int BY>
 __global__ void __launch_bounds__(BX * BY) LBM_COLLIDE_OCC k_collide(StepArgs<T, S> a) {
   constexpr int HX = BX + 2, HY = BY + 2, HN = HX * HY, NT = BX * BY;
+  constexpr int KR = (HN + NT - 1) / NT;   // records staged per thread and plane
   __shared__ V4<T> ring[4][HN];
   const int g = *a.gstep;
   const int s = (int)blockIdx.y;
@@ -253,23 +274,34 @@ __global__ void __launch_bounds__(BX * BY) LBM_COLLIDE_OCC k_collide(StepArgs<T,
     T* __restrict__ rho_out = a.P.rho[par ^ 1] + 2 * R.off + s * N;
     T* __restrict__ j_out = a.P.j[par ^ 1] + 6 * R.off + 3 * s * N;
     const V4<T>* __restrict__ rec = (s == 0 ? a.P.recA : a.P.recB) + R.off;
-    const int xm = x == 0 ? nx - 1 : x - 1, xp = x >= nx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? ny - 1 : y - 1, yp = y >= ny - 1 ? 0 : y + 1;
+    // inactive threads of a ragged tile address the edge node (their loads
+    // are in bounds and their values unused)
+    const int xq = x < nx ? x : nx - 1, yq = y < ny ? y : ny - 1;
+    const int xm = xq == 0 ? nx - 1 : xq - 1, xp = xq >= nx - 1 ? 0 : xq + 1;
+    const int ym = yq == 0 ? ny - 1 : yq - 1, yp = yq >= ny - 1 ? 0 : yq + 1;
+    // run parameters in registers: a load of them inside the z-march would
+    // wait for the populations in flight as well
     const T uw = T(R.u_wall);
     const T it = T(R.inv_tau[s]);
+    const uint32_t hstep = ((uint32_t)(R.base + g) * 2u + (uint32_t)s) * 0x85ebca77u;
     using St = Store<T, S>;
     const T kS = T(St::kScale), ikS = T(1.0 / St::kScale);
-    // copy plane zp of the tile + halo (periodic in x and y) into its slot;
-    // positions beyond a ragged edge hold valid but unused nodes
-    auto stage = [&](int zp) {
-      V4<T>* __restrict__ sl = ring[zp & 3];
-      for (int k = tid; k < HN; k += NT) {
-        int gx = (tl.x0 + k % HX - 1) % nx;
-        int gy = (tl.y0 + k / HX - 1) % ny;
-        gx += gx < 0 ? nx : 0;
-        gy += gy < 0 ? ny : 0;
-        sl[k] = rec[nid(gx, gy, zp, nx, ny)];
-      }
+    // records of plane zp of the tile + halo (periodic in x and y), the
+    // kk-th of each thread: loaded into registers ahead of the populations,
+    // so that writing them to the ring waits for these loads only.  Threads
+    // past the halo's end load and rewrite its last record (no branch, so
+    // the loads stay where they are issued).
+    static_assert(KR <= 3, "at most three records per thread and plane");
+    auto rec_at = [&](int zp, int kk) -> V4<T> {
+      const int k = min(tid + kk * NT, HN - 1);
+      int gx = (tl.x0 + k % HX - 1) % nx;
+      int gy = (tl.y0 + k / HX - 1) % ny;
+      gx += gx < 0 ? nx : 0;
+      gy += gy < 0 ? ny : 0;
+      return rec[nid(gx, gy, zp, nx, ny)];
+    };
+    auto rec_put = [&](int zp, int kk, const V4<T>& v) {
+      ring[zp & 3][min(tid + kk * NT, HN - 1)] = v;
     };
     // Byte offsets inside one direction array (a run's array is < 4 GiB, which
     // the library checks): the plane term is uniform, rows and columns
@@ -277,9 +309,9 @@ __global__ void __launch_bounds__(BX * BY) LBM_COLLIDE_OCC k_collide(StepArgs<T,
     // population access is a uniform base plus one 32-bit offset.
     constexpr uint32_t SB = sizeof(S);
     const uint32_t pb = (uint32_t)nx * (uint32_t)ny * SB;
-    const uint32_t rowb[3] = {(uint32_t)(ym * nx) * SB, (uint32_t)(y * nx) * SB,
+    const uint32_t rowb[3] = {(uint32_t)(ym * nx) * SB, (uint32_t)(yq * nx) * SB,
                               (uint32_t)(yp * nx) * SB};
-    const uint32_t colb[3] = {(uint32_t)xm * SB, (uint32_t)x * SB, (uint32_t)xp * SB};
+    const uint32_t colb[3] = {(uint32_t)xm * SB, (uint32_t)xq * SB, (uint32_t)xp * SB};
     auto arr = [&](const S* base, int i, uint32_t off) {
       return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base + (int64_t)i * N) + off);
     };
@@ -304,14 +336,28 @@ __global__ void __launch_bounds__(BX * BY) LBM_COLLIDE_OCC k_collide(StepArgs<T,
     };
     __syncthreads();   // the previous tile's readers are done with the ring
     const int zend = min(tl.z0 + a.bz, nz);
-    if (tl.z0 > 0) stage(tl.z0 - 1);
-    stage(tl.z0);
+    for (int zp = max(tl.z0 - 1, 0); zp <= tl.z0; ++zp)
+      for (int kk = 0; kk < KR; ++kk) rec_put(zp, kk, rec_at(zp, kk));
     // software pipeline: the populations of plane z+1 are in flight while
     // plane z is collided; the two register sets alternate roles (the march
-    // is unrolled by two planes), so no copy is made between planes
+    // is unrolled by two planes), so no copy is made between planes.  The
+    // loads are unconditional (past the tile's end they re-read its last
+    // plane, past the lattice's end its top plane): a load skipped on some
+    // path would make the compiler wait for all of them before plane z.
     auto plane = [&](int z, T (&cur)[Q], T (&nxt)[Q]) {
-      if (active && z + 1 < zend) load_plane(z + 1, nxt);
-      if (z + 1 < nz) stage(z + 1);
+      {
+        const int zr = min(z + 1, nz - 1);
+        const V4<T> r0 = rec_at(zr, 0);
+        const V4<T> r1 = KR > 1 ? rec_at(zr, 1) : r0;
+        const V4<T> r2 = KR > 2 ? rec_at(zr, 2) : r0;
+        __builtin_amdgcn_sched_barrier(0);   // the record loads issue first
+        load_plane(min(z + 1, zend - 1), nxt);
+        if (z + 1 < nz) {
+          rec_put(z + 1, 0, r0);
+          if (KR > 1) rec_put(z + 1, 1, r1);
+          if (KR > 2) rec_put(z + 1, 2, r2);
+        }
+      }
       __syncthreads();
       if (active) {
         const int64_t n = nid(x, y, z, nx, ny);
@@ -363,8 +409,7 @@ __global__ void __launch_bounds__(BX * BY) LBM_COLLIDE_OCC k_collide(StepArgs<T,
         // directions (uniform for every direction, independent of the tile
         // shape and batch layout, and reproducible).
         uint32_t hb = 0;
-        if (St::kRandom)
-          hb = fmix32((uint32_t)n * 0x9e3779b1u ^ ((uint32_t)(R.base + g) * 2u + (uint32_t)s) * 0x85ebca77u);
+        if (St::kRandom) hb = fmix32((uint32_t)n * 0x9e3779b1u ^ hstep);
         T jx = 0, jy = 0, jz = 0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -387,7 +432,7 @@ __global__ void __launch_bounds__(BX * BY) LBM_COLLIDE_OCC k_collide(StepArgs<T,
       }
     };
     T va[Q], vb[Q];
-    if (active) load_plane(tl.z0, va);
+    load_plane(tl.z0, va);
     for (int z = tl.z0; z < zend; z += 2) {
       plane(z, va, vb);
       if (z + 1 < zend) plane(z + 1, vb, va);
