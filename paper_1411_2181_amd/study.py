@@ -4,8 +4,11 @@ reference.
 
     python -m paper_1411_2181_amd.study generate DATA.json [--runs 160] [--skip 0] [--near D1.json]
     python -m paper_1411_2181_amd.study search OUT.json --data DATA.json[,DATA2.json] \
-        [--queries 16] [--fp64-queries 1] [--precision fp32|fp16s]
+        [--queries 32] [--fp64-queries 1] [--precision fp32|fp16s]
     python -m paper_1411_2181_amd.study elongation OUT.json --search SEARCH.json [--queries 4]
+    python -m paper_1411_2181_amd.study fp64 OUT.json [--queries 4] [--compare SEARCH.json]
+    python -m paper_1411_2181_amd.study scan OUT.json --De 1.2 --c 0.63 --fraction 0.2 \
+        --ca 0.18,0.2,0.22 [--t-end 16000]
 
 Study window (the part of parameter space where the droplet breaks at a
 reachable capillary number and keeps its volume): R = 24 (Reynolds number
@@ -329,6 +332,72 @@ def cmd_elongation(args, log):
     return 0
 
 
+def cmd_fp64(args, log):
+    """Plain bisection in FP64, one run at a time (the reference path), on
+    the first --queries query triples; with --compare, each located Ca_cr is
+    set beside the batched plain search's for the same triple."""
+    qs = query_searches(args.queries)
+    ref = None
+    if args.compare:
+        with open(args.compare) as fh:
+            ref = json.load(fh)["search"]["rows"]
+    rows, total, runs = [], 0.0, 0
+    for k, q in enumerate(qs):
+        lo, hi = window(q)
+        s64 = [sweep.Search(q["De"], q["lam"], q["c"], q["R"], lo, hi, hard_lo=lo, hard_hi=hi,
+                            L2=q["L2"], fraction=q["fraction"])]
+        s64, t, _ = sweep.bisect(s64, tol=TOL, run=single_runner("fp64", log))
+        a = s64[0]
+        total += t
+        runs += a.runs
+        row = dict(q, seconds=t, runs=a.runs, ca_cr=a.ca_cr, bracket=[a.lo, a.hi], outside=a.outside)
+        if ref is not None:
+            r = ref[k]["plain"]
+            row["batched_plain"] = dict(ca_cr=r["ca_cr"], bracket=r["bracket"], outside=r["outside"])
+            row["same_bracket"] = (r["outside"] == a.outside and abs(r["bracket"][0] - a.lo) < 1e-12
+                                   and abs(r["bracket"][1] - a.hi) < 1e-12)
+        rows.append(row)
+        log(f"fp64 single: query {k + 1} {t:.1f} s, {a.runs} runs, Ca_cr {a.ca_cr:.3f} "
+            f"({a.outside or 'inside'})" + (f", same bracket as batched: {row['same_bracket']}"
+                                              if ref is not None else ""))
+    out = dict(queries=len(qs), tol=TOL, t_end=T_END, seconds=total, runs=runs,
+               sweeps_per_hour=len(qs) / total * 3600, rows=rows)
+    with open(args.out, "w") as fh:
+        json.dump(out, fh, indent=1, default=_plain)
+    log(f"fp64 single: {len(qs)} queries, {total:.1f} s, {runs} runs, "
+        f"{out['sweeps_per_hour']:.1f} sweeps per hour")
+    return 0
+
+
+def cmd_scan(args, log):
+    """Break-up against Ca at one (De, lambda, c) point: every Ca of the list
+    runs for up to --t-end steps in one batch, checked every --every steps,
+    with its break-up step, daughter sizes and elongation history.  Shows
+    where break-up is not monotonic in Ca (a stable window above a breaking
+    Ca), which bisection cannot see."""
+    lam, f = window_lambda(args.De, args.fraction)
+    cas = [float(v) for v in args.ca.split(",")]
+    specs = [sweep.RunSpec(args.R, args.c, ca, args.De, lam, args.L2, f) for ca in cas]
+    res, sec = sweep.simulate(specs, args.precision, t_end=args.t_end, every=args.every, progress=log)
+    rows = []
+    for ca, r in zip(cas, res):
+        tem = r.info["tau_em"]
+        hist = [dict(step=h[0], D=h[1], theta=h[2], Lp_over_2R=h[3] / (2 * args.R), pieces=h[4])
+                for h in r.history]
+        rows.append(dict(Ca=ca, broken=r.broken, step_break=r.step_break, status=r.status,
+                         t_break_over_tau_em=(r.step_break / tem) if r.broken else None,
+                         daughter_nodes=r.pieces, Lp_max_over_2R=max(h["Lp_over_2R"] for h in hist),
+                         history=hist))
+        log(f"Ca={ca:.3f}: " + (f"breaks at {r.step_break} into {len(r.pieces)} {r.pieces}" if r.broken
+                                 else "stable") + f", max Lp/2R {rows[-1]['Lp_max_over_2R']:.2f}")
+    out = dict(De=args.De, lam=lam, fraction=f, c=args.c, R=args.R, L2=args.L2,
+               precision=args.precision, t_end=args.t_end, every=args.every, seconds=sec,
+               tau_em=res[0].info["tau_em"], rows=rows)
+    with open(args.out, "w") as fh:
+        json.dump(out, fh, indent=1, default=_plain)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -341,7 +410,7 @@ def main(argv=None):
     s = sub.add_parser("search")
     s.add_argument("out")
     s.add_argument("--data", required=True, help="comma-separated generate outputs")
-    s.add_argument("--queries", type=int, default=16)
+    s.add_argument("--queries", type=int, default=32)
     s.add_argument("--epochs", type=int, default=3000)
     s.add_argument("--fp64-queries", type=int, default=1)
     s.add_argument("--precision", default="fp32", choices=["fp32", "fp16s"],
@@ -351,9 +420,25 @@ def main(argv=None):
     e.add_argument("--search", required=True, help="a search output (brackets of located Ca_cr)")
     e.add_argument("--queries", type=int, default=4)
     e.add_argument("--every", type=int, default=500)
+    f64 = sub.add_parser("fp64")
+    f64.add_argument("out")
+    f64.add_argument("--queries", type=int, default=4)
+    f64.add_argument("--compare", default="", help="a search output of the same query triples")
+    k = sub.add_parser("scan")
+    k.add_argument("out")
+    k.add_argument("--De", type=float, required=True)
+    k.add_argument("--c", type=float, required=True)
+    k.add_argument("--fraction", type=float, default=0.4)
+    k.add_argument("--L2", type=float, default=100.0)
+    k.add_argument("--R", type=float, default=24.0)
+    k.add_argument("--ca", required=True, help="comma-separated capillary numbers")
+    k.add_argument("--t-end", type=int, default=T_END)
+    k.add_argument("--every", type=int, default=500)
+    k.add_argument("--precision", default="fp32", choices=["fp32", "fp16s"])
     args = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
-    cmd = {"generate": cmd_generate, "search": cmd_search, "elongation": cmd_elongation}
+    cmd = {"generate": cmd_generate, "search": cmd_search, "elongation": cmd_elongation,
+           "scan": cmd_scan, "fp64": cmd_fp64}
     return cmd[args.cmd](args, log)
 
 

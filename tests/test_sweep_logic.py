@@ -102,3 +102,20 @@ def test_runs_carry_the_search_polymer_parameters():
     s = sweep.Search(1.0, 4 / 3, 0.5, 24.0, 0.10, 0.26, hard_lo=0.10, hard_hi=0.26, L2=400.0, fraction=0.2)
     sweep.bisect([s], tol=TOL, run=run)
     assert seen and all(v == (400.0, 0.2) for v in seen)
+
+
+def test_lattice_runner_logs_each_round(monkeypatch):
+    class Res:
+        def __init__(self, sp):
+            self.broken, self.status, self.steps = sp.Ca > 0.18, 0, 100
+            self.params = dict(nx=4, ny=5, nz=6)
+
+    def fake_simulate(specs, precision, **kw):
+        return [Res(sp) for sp in specs], 0.5 * len(specs)
+    monkeypatch.setattr(sweep, "simulate", fake_simulate)
+    run = sweep.lattice_runner("fp16s")
+    (s,), secs, rounds = sweep.bisect([search(0.10, 0.26)], tol=TOL, run=run)
+    assert len(run.rounds) == rounds
+    assert sum(r[0] for r in run.rounds) == s.runs
+    assert all(r[1] == r[0] * 100 * 120 and r[2] == 0.5 * r[0] for r in run.rounds)
+    assert secs == sum(r[2] for r in run.rounds)

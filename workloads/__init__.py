@@ -167,11 +167,17 @@ def surrogate_window_sampler(k: int, base_seed: int = 98765) -> dict:
 
 
 def query_window(n: int = 16, seed: int = 4242) -> list[dict]:
-    """(De, c) query pairs inside the study window (L^2 = 100, polymer
-    fraction 0.4, R = 24; the viscosity ratio follows from the fraction)."""
+    """Query triples (De, lambda, c) inside the study window: De ~ U[0.25, 2],
+    c ~ U[0.45, 0.65], polymer fraction in {0.2, 0.4} (the viscosity ratio
+    follows from it by the window's solvent rule), L^2 = 100, R = 24."""
     rng = np.random.default_rng(seed)
-    return [dict(De=float(rng.uniform(0.25, 2.0)), confinement=float(rng.uniform(0.45, 0.65)),
-                 L2=100.0, polymer_fraction=0.4, R=24.0) for _ in range(n)]
+    out = []
+    for _ in range(n):
+        De = float(rng.uniform(0.25, 2.0))
+        c = float(rng.uniform(0.45, 0.65))
+        f = float(rng.choice([0.2, 0.4]))
+        out.append(dict(De=De, confinement=c, L2=100.0, polymer_fraction=f, R=24.0))
+    return out
 
 
 # ----------------------------------------------------------------------------
