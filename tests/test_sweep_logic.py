@@ -119,3 +119,36 @@ def test_lattice_runner_logs_each_round(monkeypatch):
     assert sum(r[0] for r in run.rounds) == s.runs
     assert all(r[1] == r[0] * 100 * 120 and r[2] == 0.5 * r[0] for r in run.rounds)
     assert secs == sum(r[2] for r in run.rounds)
+
+
+def test_fp64_reference_search_compares_brackets(monkeypatch, tmp_path):
+    import json
+    import types
+    from paper_1411_2181_amd import study
+
+    class Res:
+        def __init__(self, sp):
+            self.broken, self.status, self.steps = sp.Ca > 0.185, 0, 100
+            self.params = dict(nx=4, ny=5, nz=6)
+
+    def fake_simulate(specs, precision, **kw):
+        assert precision == "fp64" and len(specs) == 1      # one run at a time
+        return [Res(sp) for sp in specs], 2.0
+    monkeypatch.setattr(sweep, "simulate", fake_simulate)
+    # the batched search's rows for the same triples: the first agrees, the second not
+    qs = study.query_searches(2)
+    rows = []
+    for k, q in enumerate(qs):
+        s, _, _ = sweep.bisect([sweep.Search(q["De"], q["lam"], q["c"], q["R"], *study.window(q),
+                                             hard_lo=study.window(q)[0], hard_hi=study.window(q)[1])],
+                               tol=study.TOL, run=lambda specs: ([(sp.Ca > 0.185, 0) for sp in specs], 0.0))
+        lo, hi = (s[0].lo, s[0].hi) if k == 0 else (s[0].lo + 0.01, s[0].hi + 0.01)
+        rows.append(dict(plain=dict(ca_cr=0.5 * (lo + hi), bracket=[lo, hi], outside="")))
+    ref = tmp_path / "search.json"
+    ref.write_text(json.dumps(dict(search=dict(rows=rows))))
+    out = tmp_path / "fp64.json"
+    study.cmd_fp64(types.SimpleNamespace(out=str(out), queries=2, compare=str(ref)), lambda m: None)
+    d = json.loads(out.read_text())
+    assert [r["same_bracket"] for r in d["rows"]] == [True, False]
+    assert d["seconds"] == 2.0 * d["runs"]
+    assert abs(d["sweeps_per_hour"] - 2 / d["seconds"] * 3600) < 1e-9
