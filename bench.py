@@ -1,6 +1,6 @@
 """Throughput of the hybrid LB / FENE-P step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32] [--box 512x256x128]
 
 Workload: the matrix-viscoelastic droplet in confined shear on a 512x256x128
 lattice (W = 128), droplet R = 32 (2R/W = 0.5) at mid-gap, FENE-P in the
@@ -17,7 +17,8 @@ events around each pass in a second region of the same length on the same
 stream.  The roofline is given for the dominant kernel (collide-stream) and
 for the whole step; measured HBM traffic per dispatch comes from the
 committed rocprofv3 counter summary (profiles/traffic_mv512.json) while the
-kernel sources are unchanged.
+kernel sources are unchanged.  A 1 GiB device-to-device copy timed in the
+same process gives the measured bandwidth ceiling beside the 8 TB/s peak.
 """
 from __future__ import annotations
 
@@ -31,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BOX = (512, 256, 128)
 METRIC = "MLUPS (D3Q19x2 + FENE-P), % HBM roofline; Ca_cr sweeps/hour at +/-0.01"
 # algorithmic bytes per lattice update: read and write every population of
 # both components and every conformation component once
@@ -62,10 +64,10 @@ def workload_params(nx=512, ny=256, nz=128, u_wall=0.1):
     return p, info
 
 
-def measured_traffic(precision, launch):
+def measured_traffic(precision, launch, box=BOX):
     """HBM bytes per dispatch of each step kernel at this launch shape, from
     the committed rocprofv3 counter summary, if it was taken on the current
-    kernel sources (else None)."""
+    kernel sources and the same lattice (else None)."""
     from paper_1411_2181_amd.build import source_hash
     path = os.path.join(ROOT, "profiles", "traffic_mv512.json")
     if not os.path.exists(path):
@@ -75,16 +77,18 @@ def measured_traffic(precision, launch):
     entry = t.get(precision)
     if not entry or entry.get("source_hash") != source_hash():
         return None
+    if tuple(entry.get("box", BOX)) != tuple(box):
+        return None
     # a persistent grid over the same tiles is taken to move the same bytes
     return entry["launches"].get(f"{launch['bx']}x{launch['by']}x{launch['bz']}")
 
 
-def gpu_run(precision, steps, warmup, launch=None):
+def gpu_run(precision, steps, warmup, launch=None, box=BOX):
     """Autotune (unless ``launch`` pins the shape), then the graph-replayed
     timed region, then ``steps`` eager steps with HIP events per pass."""
     import torch
     from paper_1411_2181_amd import autotune, lbmve
-    p, info = workload_params()
+    p, info = workload_params(*box)
     s = lbmve.Solver(p, precision)
     if launch:
         s.set_launch(**launch)
@@ -104,7 +108,26 @@ def gpu_run(precision, steps, warmup, launch=None):
     s.close()
     wall = t1 - t0
     return dict(nodes=nodes, wall=wall, ms=[m / steps for m in ms], obs=obs, params=p,
-                info=info, launch=launch, tuned=tuned)
+                info=info, launch=launch, tuned=tuned, box=tuple(box))
+
+
+def copy_bandwidth(gib=1, reps=5):
+    """Measured ceiling for comparison: a device-to-device copy of ``gib`` GiB
+    (read + written), timed with HIP events on the current stream; GB/s."""
+    import torch
+    n = (gib << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * (gib << 30) / (ms * 1e-3) / 1e9
 
 
 def pmc_pass(precision, steps=4, launch=None):
@@ -165,7 +188,7 @@ def roofline(precision, r):
     step_ms = ms_force + ms_coll + ms_fene
     balg = B_ALG[precision]
     step_ach = balg * nodes / (step_ms * 1e-3) / 1e9
-    tr = measured_traffic(precision, r["launch"])
+    tr = measured_traffic(precision, r["launch"], r.get("box", BOX))
     step = {
         "kernels": "k_force + k_collide + k_fene",
         "bytes_alg_per_update": balg,
@@ -204,7 +227,11 @@ def main():
                     help="short run for rocprofv3 counter collection (prints no JSON)")
     ap.add_argument("--launch", default="",
                     help="pin the launch shape BXxBYxBZ[xP] instead of autotuning (profiling runs)")
+    ap.add_argument("--box", default="512x256x128",
+                    help="lattice NXxNYxNZ (default: the full case; 64x256x128 is one GPU's "
+                         "x-slab of it in an 8-way decomposition)")
     args = ap.parse_args()
+    box = tuple(int(t) for t in args.box.lower().split("x"))
     launch = None
     if args.launch:
         v = [int(t) for t in args.launch.lower().split("x")]
@@ -219,7 +246,7 @@ def main():
         pmc_pass(args.precision, launch=launch)
         return
 
-    r = gpu_run(args.precision, args.steps, args.warmup, launch)
+    r = gpu_run(args.precision, args.steps, args.warmup, launch, box)
     nodes, wall = r["nodes"], r["wall"]
     mlups = nodes * args.steps / wall / 1e6
     out = {
@@ -236,7 +263,8 @@ def main():
         "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {
-            "workload": "matrix-viscoelastic droplet in confined shear, 512x256x128 (W=128), "
+            "workload": "matrix-viscoelastic droplet in confined shear, "
+                        f"{box[0]}x{box[1]}x{box[2]} (W={box[2]}), "
                         "R=32, FENE-P in matrix L2=400 De=1 fraction 0.4, lambda=0.5, "
                         f"Ca={r['info']['Ca']:.3f} (U_w=0.1)",
             "nodes": nodes,
@@ -250,11 +278,16 @@ def main():
     }
     variants = [v for v in args.variants.split(",") if v and v != args.precision]
     for v in variants:
-        rv = gpu_run(v, args.steps, args.warmup)
+        rv = gpu_run(v, args.steps, args.warmup, box=box)
         mv = rv["nodes"] * args.steps / rv["wall"] / 1e6
         out[f"variant_{v}"] = {"value": round(mv, 1), "unit": "MLUPS",
                                "ms_per_step": round(rv["wall"] / args.steps * 1e3, 4),
                                "launch": rv["launch"], "roofline": roofline(v, rv)}
+    out["roofline"]["copy_ceiling"] = {
+        "what": "1 GiB device-to-device copy (read + written), HIP events",
+        "GBs": round(copy_bandwidth(), 1)}
+    out["roofline"]["copy_ceiling"]["frac"] = round(out["roofline"]["copy_ceiling"]["GBs"] /
+                                                    HBM_PEAK_GBS, 4)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

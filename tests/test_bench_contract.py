@@ -26,7 +26,7 @@ def _fake_run(ms=(0.4, 1.25, 0.3), launch=(32, 8, 16)):
 
 def test_roofline_fields_and_arithmetic(monkeypatch):
     import bench
-    monkeypatch.setattr(bench, "measured_traffic", lambda p, l: None)
+    monkeypatch.setattr(bench, "measured_traffic", lambda p, l, b=None: None)
     r = bench.roofline("fp32", _fake_run())
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "step"):
         assert k in r
@@ -52,8 +52,9 @@ def test_traffic_lookup_needs_matching_sources(tmp_path, monkeypatch):
         (prof / "traffic_mv512.json").write_text(json.dumps(
             {"fp32": {"source_hash": h, "launches": {"32x8x16": entry}}}))
         assert bench.measured_traffic("fp32", _fake_run()["launch"]) == want
-    # a shape that was not measured, and a precision that was not
+    # a shape that was not measured, a precision that was not, another lattice
     assert bench.measured_traffic("fp32", dict(bx=64, by=4, bz=8, persistent=0)) is None
     assert bench.measured_traffic("fp16s", _fake_run()["launch"]) is None
+    assert bench.measured_traffic("fp32", _fake_run()["launch"], (64, 256, 128)) is None
     r = bench.roofline("fp32", _fake_run())
     assert r["traffic"] == 2 and r["step"]["traffic_per_update"] == 500.0
