@@ -2,7 +2,7 @@
  * lbmve surrogate — a small learned model that proposes where to bracket the
  * critical capillary number Ca_cr of droplet break-up (the quantity the
  * paper locates by pre/post-critical wall speeds, Section 3).  The plain
- * simulation stays the judge: every proposal is verified by full runs.
+ * simulation stays the arbiter: every proposal is verified by full runs.
  *
  * Network: inputs (Ca, De, lambda, 2R/W, L^2, polymer fraction) -- the
  * dimensionless groups of Sections 2-3, z-scored by the caller -- through

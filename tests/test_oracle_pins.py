@@ -220,7 +220,7 @@ def test_fene_p_homogeneous_shear_matches_paper(wi, L2):
     assert np.abs(C[3]).max() < 1e-15 and np.abs(C[5]).max() < 1e-15
 
 
-def test_fene_p_survey_table_row():
+def test_fene_p_peterlin_consistency_at_wi_1():
     # Wi = 1, L^2 = 100: f^2 (f - 1) = 2 Wi^2 / L^2 (consistency of Eq. (6)
     # with the Peterlin factor); f = 1.019251615479
     s, _ = _paper_eq6_eq7(1.0, 100.0)
