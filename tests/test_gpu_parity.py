@@ -311,3 +311,48 @@ def test_reduced_precision_mass_drift(lbm, precision):
     print(f"{precision}: relative mass drift {drift}")
     assert max(drift) < 1e-5
     s.close()
+
+
+# ---- full size, in the bench's launch configuration ----------------------------
+# One step of the 512x256x128 matrix-viscoelastic workload after 100 steps of
+# flow, checked on sampled columns: the oracle advances a 9x9x128 column block
+# cut from the GPU's state (periodic in x and y like the lattice).  A node's
+# update reads the state within radius 2, so the block's centre column is
+# exact although the block's own periodic wrap is not the lattice's.
+FULL_COLUMNS = [(255, 127), (256, 128), (223, 127), (288, 128),   # droplet, interface
+                (31, 7), (32, 8), (0, 0), (511, 255), (100, 200)]  # tile and periodic seams
+
+
+def _column_block(a, x, y, nx, ny, h=4):
+    xi = np.arange(x - h, x + h + 1) % nx
+    yi = np.arange(y - h, y + h + 1) % ny
+    return np.ascontiguousarray(a[..., yi, :][..., xi])
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_full_size_one_step_sampled(lbm, precision, tol):
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    p, _ = bench.workload_params()
+    nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    print(f"case full size {nx}x{ny}x{nz} {precision}, launch 32x8x64 persistent 2048", flush=True)
+    s = lbm.Solver(p, precision)
+    s.set_launch(bx=32, by=8, bz=64, persistent=2048)
+    s.step(100)
+    f0, C0 = s.export("f"), s.export("C")
+    s.step(1)
+    f1, C1 = s.export("f"), s.export("C")
+    s.close()
+    fmax, cmax = max(f1.max(), -f1.min()), max(C1.max(), -C1.min())
+    for x, y in FULL_COLUMNS:
+        d = dict(p, nx=9, ny=9)
+        o = Oracle(d, f=_column_block(f0, x, y, nx, ny), C=_column_block(C0, x, y, nx, ny))
+        o.step(1)
+        ef = np.abs(o.f[..., 4, 4] - f1[..., y, x]).max() / fmax
+        eC = np.abs(o.C[..., 4, 4] - C1[..., y, x]).max() / cmax
+        print(f"  column ({x}, {y}): f {ef:.1e}, C {eC:.1e}", flush=True)
+        assert o.status == 0
+        assert ef <= tol and eC <= tol, (x, y, ef, eC)
