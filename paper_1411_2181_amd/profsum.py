@@ -3,6 +3,7 @@
     python -m paper_1411_2181_amd.profsum trace KERNEL_TRACE.csv [--box 512,256,128]
     python -m paper_1411_2181_amd.profsum traffic FETCH.csv WRITE.csv --precision fp32 \
         [--json profiles/traffic_mv512.json] [--box 512,256,128]
+    python -m paper_1411_2181_amd.profsum sq SQ_COUNTERS.csv [--box 512,256,128]
 
 ``trace`` groups the dispatches of a ``--kernel-trace`` run by kernel and
 launch shape (bx x by x bz, recovered from the grid size and the box) and
@@ -121,6 +122,39 @@ def traffic_table(fetch_csv, write_csv, box):
     return table, scale
 
 
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
+               "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES")
+SIMDS, CLOCK_HZ = 1024, 2.4e9          # MI355X: 256 CUs x 4 SIMDs, 2.4 GHz
+
+
+def sq_table(path, box):
+    """Per step kernel: instructions per lattice node (per-wave counts x 64
+    lanes / nodes) and the VALU issue share, the fraction of the SIMDs'
+    cycles over the dispatch that its VALU instructions occupy (4 cycles per
+    wave64 instruction)."""
+    nodes = box[0] * box[1] * box[2]
+    acc = defaultdict(lambda: defaultdict(list))
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            m = _STEP.search(r["Kernel_Name"])
+            if not m:
+                continue
+            k = f"k_{m.group(1)}"
+            acc[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+            acc[k]["_dur"].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    rows = []
+    for k, c in acc.items():
+        mean = {n: statistics.mean(v) for n, v in c.items() if v}
+        per = lambda n: mean.get(n, 0.0) * 64.0 / nodes
+        dur = mean["_dur"] * 1e-9
+        rows.append(dict(kernel=k, valu=per("SQ_INSTS_VALU"), lds=per("SQ_INSTS_LDS"),
+                         vmem_rd=per("SQ_INSTS_VMEM_RD"), vmem_wr=per("SQ_INSTS_VMEM_WR"),
+                         valu_share=mean.get("SQ_INSTS_VALU", 0.0) * 4.0 / (SIMDS * CLOCK_HZ * dur),
+                         wait_frac=mean.get("SQ_WAIT_INST_ANY", 0.0) / max(mean.get("SQ_WAVE_CYCLES", 1.0), 1.0)))
+    rows.sort(key=lambda r: r["kernel"])
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -129,6 +163,9 @@ def main(argv=None):
     t.add_argument("--box", default="512,256,128")
     t.add_argument("--tail", type=int, default=0)
     t.add_argument("--launch", default=None, help="label of the pinned launch shape")
+    q = sub.add_parser("sq")
+    q.add_argument("csv")
+    q.add_argument("--box", default="512,256,128")
     p = sub.add_parser("traffic")
     p.add_argument("fetch_csv")
     p.add_argument("write_csv")
@@ -143,6 +180,13 @@ def main(argv=None):
         for r in trace_table(a.csv, box, a.tail, a.launch):
             print(f"| {r['kernel']} | {r['launch']} | {r['calls']} | {r['mean_us']:.1f} | "
                   f"{r['min_us']:.1f} | {r['max_us']:.1f} |")
+        return 0
+    if a.cmd == "sq":
+        print("| kernel | VALU / node | LDS / node | VMEM rd / node | VMEM wr / node | VALU issue share | wait / wave cycles |")
+        print("|---|---|---|---|---|---|---|")
+        for r in sq_table(a.csv, box):
+            print(f"| {r['kernel']} | {r['valu']:.0f} | {r['lds']:.1f} | {r['vmem_rd']:.1f} | "
+                  f"{r['vmem_wr']:.1f} | {r['valu_share'] * 100:.0f} % | {r['wait_frac'] * 100:.0f} % |")
         return 0
     table, scale = traffic_table(a.fetch_csv, a.write_csv, box)
     print(f"copy-reference scale factors: FETCH_SIZE x{scale['fetch']:.4f}, WRITE_SIZE x{scale['write']:.4f}")
