@@ -9,7 +9,8 @@ confinement c in {0.3, 0.5, 0.7}, box 6R x 3R x 2R/c); the physics is mapped
 inside the window the lattice model reaches (viscosity ratio clipped to
 [0.6, 0.9], Ca to the wall-speed cap), which leaves the work per update
 unchanged.  Reports aggregate MLUPS and the algorithmic roofline fraction
-(352 B per update for viscoelastic runs, 304 B for Newtonian ones, FP32).
+(per update, viscoelastic / Newtonian runs: 352 / 304 B in FP32, 200 / 152 B
+in FP16S, 704 / 608 B in FP64).
 """
 from __future__ import annotations
 
@@ -22,7 +23,8 @@ import workloads as WL
 
 from . import sweep
 
-B_VISC, B_NEWT = 352, 304
+# algorithmic bytes per update (viscoelastic, Newtonian) by storage precision
+B_ALG = {"fp64": (704, 608), "fp32": (352, 304), "fp16s": (200, 152)}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -46,7 +48,7 @@ def main(argv=None):
     ap.add_argument("out")
     ap.add_argument("--runs", type=int, default=48)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--precision", default="fp32", choices=sorted(B_ALG))
     args = ap.parse_args(argv)
     import torch
     from . import autotune, lbmve
@@ -65,7 +67,8 @@ def main(argv=None):
     b.close()
     upd = sum(nodes) * args.steps
     mlups = upd / wall / 1e6
-    balg = sum(n * (B_VISC if v else B_NEWT) for n, v in zip(nodes, visc)) / sum(nodes)
+    b_visc, b_newt = B_ALG[args.precision]
+    balg = sum(n * (b_visc if v else b_newt) for n, v in zip(nodes, visc)) / sum(nodes)
     ach = balg * upd / wall / 1e9
     out = dict(runs=args.runs, steps=args.steps, precision=args.precision,
                nodes_total=sum(nodes), nodes_min=min(nodes), nodes_max=max(nodes),
