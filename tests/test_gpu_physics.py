@@ -57,3 +57,18 @@ def test_taylor_small_deformation():
     slope0 = 2.0 * D[0] / CAS[0] - D[1] / CAS[1]
     print(f"slope at Ca -> 0: {slope0:.4f} (Taylor {35.0 / 32.0:.4f})")
     assert abs(slope0 / (35.0 / 32.0) - 1.0) < 0.15
+
+
+def test_laplace_law_static_spheres():
+    """dp = 2 sigma / R for static droplets of radius 10, 12 and 14 (tau 1.25 in
+    both phases, G = 0.75, 48^3 boxes, walls at rest): the pressure jump of the
+    Shan-Chen bulk pressure times R_eff / 2 is the same sigma for every radius,
+    and equals the calibrated sigma the workloads are mapped with."""
+    from paper_1411_2181_amd import calibrate, physics
+    table = calibrate.calibrate(groups=((0.75, (1.25,)),), precision="fp64")
+    (e,) = table["entries"]
+    print(f"sigma {e['sigma']:.5f}, spread over radii {e['laplace_spread']:.2%}, "
+          f"R_eff {[round(r, 2) for r in e['radii']]}, spurious |u| {e['spurious_umax']:.1e}")
+    assert e["usable"] and e["laplace_spread"] < 0.05
+    assert e["sigma"] == pytest.approx(physics.sigma_for(1.25, 1.25, 0.75), rel=0.02)
+    assert e["spurious_umax"] < 0.05          # Shan-Chen spurious currents at the interface
