@@ -215,6 +215,15 @@ def test_batch_equals_single_runs(lbm):
             s.close()
         obs = b.observe()
         assert [o["step"] for o in obs] == steps
+        # runs given zero steps are masked: their state does not change
+        before = [b.export("f", r) for r in range(len(runs))]
+        b.step([0, 4, 0])
+        assert [b.steps_done(r) for r in range(len(runs))] == [steps[0], steps[1] + 4, steps[2]]
+        assert np.array_equal(b.export("f", 0), before[0])
+        assert np.array_equal(b.export("f", 2), before[2])
+        assert not np.array_equal(b.export("f", 1), before[1])
+        b.step([0, 0, 0])
+        assert np.array_equal(b.export("f", 0), before[0])
         b.close()
 
 
