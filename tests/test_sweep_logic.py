@@ -152,3 +152,34 @@ def test_fp64_reference_search_compares_brackets(monkeypatch, tmp_path):
     assert [r["same_bracket"] for r in d["rows"]] == [True, False]
     assert d["seconds"] == 2.0 * d["runs"]
     assert abs(d["sweeps_per_hour"] - 2 / d["seconds"] * 3600) < 1e-9
+
+
+def _logistic_surrogate(c0, s):
+    """A Surrogate whose break-up probability is a known logistic in Ca
+    (the proposal logic only, no network)."""
+    import numpy as np
+    from paper_1411_2181_amd.surrogate import Surrogate
+    sg = Surrogate.__new__(Surrogate)
+    sg.breakup_probability = lambda Ca, *a, **k: 1.0 / (1.0 + np.exp(-(np.asarray(Ca) - c0) / s))
+    return sg
+
+
+@pytest.mark.parametrize("c0,s", [(0.18, 0.002), (0.18, 0.02), (0.21, 0.01)])
+def test_proposal_brackets_the_predicted_boundary(c0, s):
+    import math
+    lo, hi = 0.12, 0.26
+    b = _logistic_surrogate(c0, s).propose(1.0, 1.0, 0.5, lo, hi, tol=TOL, grid=4096)
+    mid, half = 0.5 * (b[0] + b[1]), 0.5 * (b[1] - b[0])
+    want_half = max(TOL, s * math.log(3.0))     # quartiles of a logistic: c0 -+ s ln 3
+    if c0 + want_half <= hi and c0 - want_half >= lo:
+        assert mid == pytest.approx(c0, abs=1e-4) and half == pytest.approx(want_half, abs=1e-4)
+    assert lo <= b[0] < c0 < b[1] <= hi
+
+
+def test_proposal_edges_of_the_window():
+    lo, hi = 0.12, 0.26
+    assert _logistic_surrogate(0.40, 0.005).propose(1.0, 1.0, 0.5, lo, hi, tol=TOL) is None
+    b = _logistic_surrogate(0.05, 0.005).propose(1.0, 1.0, 0.5, lo, hi, tol=TOL)
+    assert b[0] == lo and b[1] == pytest.approx(lo + TOL, abs=1e-9)       # breaks everywhere
+    b = _logistic_surrogate(0.255, 0.001).propose(1.0, 1.0, 0.5, lo, hi, tol=TOL)
+    assert b[1] == hi and b[0] == pytest.approx(0.255 - TOL, abs=1e-3)    # clipped at the top
