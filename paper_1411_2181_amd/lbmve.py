@@ -219,6 +219,8 @@ class Batch:
         """Advance every run by ``steps`` (int) or run r by steps[r]."""
         if np.isscalar(steps):
             steps = [int(steps)] * self.nruns
+        if len(steps) != self.nruns:
+            raise ValueError(f"{len(steps)} step counts for {self.nruns} runs")
         a = (ctypes.c_int32 * self.nruns)(*[int(s) for s in steps])
         _check(lib().lbm_batch_step(self._c(), a), "step")
 
