@@ -208,6 +208,9 @@ def cmd_search(args, log):
     sg.fit(X, D, TH, BR, epochs=args.epochs, lr=2e-3)
 
     qs = query_searches(args.queries)
+    if args.only:
+        qs = [qs[int(i)] for i in args.only.split(",")]
+    ext = dict(extend_to=args.extend_to) if args.extend_to else {}
 
     def plain_searches():
         out = []
@@ -219,7 +222,7 @@ def cmd_search(args, log):
 
     prec = args.precision
     # plain bisection, batched
-    run_plain = sweep.lattice_runner(prec, log=log, t_end=T_END, every=EVERY)
+    run_plain = sweep.lattice_runner(prec, log=log, t_end=T_END, every=EVERY, **ext)
     plain, t_plain, r_plain = sweep.bisect(plain_searches(), tol=TOL, run=run_plain)
     log(f"plain bisection ({prec}): {t_plain:.1f} s, {r_plain} rounds, {sum(s.runs for s in plain)} runs")
 
@@ -234,20 +237,25 @@ def cmd_search(args, log):
         blo, bhi = b if b is not None else (lo, hi)
         prop.append(sweep.Search(q["De"], q["lam"], q["c"], q["R"], blo, bhi, hard_lo=lo, hard_hi=hi,
                                  L2=q["L2"], fraction=q["fraction"], speculate=b is not None))
-    run_sg = sweep.lattice_runner(prec, log=log, t_end=T_END, every=EVERY)
-    prop, t_sg, r_sg = sweep.bisect(prop, tol=TOL, run=run_sg)
+    run_sg = sweep.lattice_runner(prec, log=log, t_end=T_END, every=EVERY, **ext)
+    if args.plain_only:
+        prop = []
+    prop, t_sg, r_sg = sweep.bisect(prop, tol=TOL, run=run_sg) if prop else ([], 0.0, 0)
     log(f"surrogate-bracketed ({prec}): {t_sg:.1f} s, {r_sg} rounds, {sum(s.runs for s in prop)} runs")
 
     rows_q, agree, comparable = [], 0, 0
-    for q, a, b, pb in zip(qs, plain, prop, proposals):
-        rows_q.append(dict(q, window=list(window(q)), proposal=pb,
-                           plain=dict(ca_cr=a.ca_cr, bracket=[a.lo, a.hi], outside=a.outside,
-                                      runs=a.runs, rounds=a.rounds, updates=a.updates),
-                           surrogate=dict(ca_cr=b.ca_cr, bracket=[b.lo, b.hi], outside=b.outside,
-                                          runs=b.runs, rounds=b.rounds, updates=b.updates)))
-        if a.outside == b.outside:
-            comparable += 1
-            agree += (a.outside != "" or abs(a.ca_cr - b.ca_cr) <= TOL)
+    for k, (q, a, pb) in enumerate(zip(qs, plain, proposals)):
+        row = dict(q, window=list(window(q)), proposal=pb,
+                   plain=dict(ca_cr=a.ca_cr, bracket=[a.lo, a.hi], outside=a.outside,
+                              runs=a.runs, rounds=a.rounds, updates=a.updates))
+        if prop:
+            b = prop[k]
+            row["surrogate"] = dict(ca_cr=b.ca_cr, bracket=[b.lo, b.hi], outside=b.outside,
+                                    runs=b.runs, rounds=b.rounds, updates=b.updates)
+            if a.outside == b.outside:
+                comparable += 1
+                agree += (a.outside != "" or abs(a.ca_cr - b.ca_cr) <= TOL)
+        rows_q.append(row)
     # sweeps per hour at saturation: with many queries in flight the GPU is
     # full and time goes as lattice updates, not as rounds.  The saturated
     # rate is that of the largest batch either search ran (the plain search's
@@ -257,7 +265,8 @@ def cmd_search(args, log):
     upd_plain = sum(s.updates for s in plain)
     upd_sg = sum(s.updates for s in prop)
     report["search"] = dict(
-        queries=len(qs), tol=TOL, t_end=T_END, precision=prec,
+        queries=len(qs), tol=TOL, t_end=T_END, extend_to=args.extend_to, precision=prec,
+        only=args.only,
         saturated_batch=dict(runs=big[0], updates=big[1], seconds=big[2]),
         plain=dict(seconds=t_plain, rounds=r_plain, runs=sum(s.runs for s in plain),
                    updates=upd_plain, sweeps_per_hour=len(qs) / t_plain * 3600,
@@ -265,7 +274,8 @@ def cmd_search(args, log):
         surrogate=dict(seconds=t_sg, rounds=r_sg, runs=sum(s.runs for s in prop),
                        updates=upd_sg, sweeps_per_hour=len(qs) / t_sg * 3600,
                        sweeps_per_hour_saturated=len(qs) / (upd_sg / rate) * 3600,
-                       first_round_hits=sum(1 for s in prop if s.rounds == 1 and s.outside == "")),
+                       first_round_hits=sum(1 for s in prop if s.rounds == 1 and s.outside == ""))
+        if prop else None,
         batched_rate_mlups=rate / 1e6,
         same_outcome=comparable, agree_within_tol=agree, rows=rows_q)
 
@@ -415,6 +425,10 @@ def main(argv=None):
     s.add_argument("--fp64-queries", type=int, default=1)
     s.add_argument("--precision", default="fp32", choices=["fp32", "fp16s"],
                    help="storage of the batched searches")
+    s.add_argument("--extend-to", type=int, default=0,
+                   help="run a droplet still elongating at the horizon on, up to this step")
+    s.add_argument("--only", default="", help="comma-separated indices of the query triples")
+    s.add_argument("--plain-only", action="store_true", help="skip the surrogate's search")
     e = sub.add_parser("elongation")
     e.add_argument("out")
     e.add_argument("--search", required=True, help="a search output (brackets of located Ca_cr)")

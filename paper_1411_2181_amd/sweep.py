@@ -59,6 +59,19 @@ class RunResult:
     status: int = 0
     pieces: list = field(default_factory=list)   # node counts of the pieces at break-up
     history: list = field(default_factory=list)
+    extended: bool = False   # ran past its end time because it was still elongating
+
+
+def still_elongating(history, window: int = 4000) -> bool:
+    """True when the droplet's length L_p at the last check exceeds its length
+    ``window`` steps earlier (the latest check at or before that step).  A
+    droplet that stays whole relaxes or holds its length; one that is still
+    stretching at the end of a run may yet break."""
+    if not history:
+        return False
+    last_step, last_lp = history[-1][0], history[-1][3]
+    earlier = [h for h in history if h[0] <= last_step - window]
+    return bool(earlier) and last_lp > earlier[-1][3]
 
 
 def box(R: float, c: float):
@@ -91,12 +104,15 @@ def lattice(spec: RunSpec):
 
 def simulate(specs, precision: str = "fp32", t_end: int | None = None, every: int = 1000,
              min_steps: int = 4000, max_steps: int = 40000, device="cuda:0", launch=None,
-             progress=None):
+             progress=None, extend_to: int = 0, grow_window: int = 4000):
     """Advance every run (one batch) to its end time, checking for break-up
-    every ``every`` steps; a broken run is stopped (masked) at once.  Steady
-    D and orientation are averaged over the last three checks of unbroken
-    runs; ``progress`` (a callable) receives a line after every check.
-    Returns (results, seconds)."""
+    every ``every`` steps; a broken run is stopped (masked) at once.  With
+    ``extend_to`` > 0, a run still whole at its end time whose droplet is
+    still elongating (still_elongating over ``grow_window`` steps) goes on,
+    check by check, until it breaks, stops elongating or reaches
+    ``extend_to`` steps.  Steady D and orientation are averaged over the last
+    three checks of unbroken runs; ``progress`` (a callable) receives a line
+    after every check.  Returns (results, seconds)."""
     results, runs = [], []
     for sp in specs:
         p, info = lattice(sp)
@@ -132,6 +148,10 @@ def simulate(specs, precision: str = "fp32", t_end: int | None = None, every: in
                 r.step_break = o["step"]
                 r.pieces = [v for v in o["piece_nodes"] if v > 0]
                 remaining[k] = 0
+            elif (remaining[k] == 0 and extend_to > r.steps
+                  and still_elongating(r.history, grow_window)):
+                r.extended = True
+                remaining[k] = min(every, extend_to - r.steps)
         if progress:
             progress(f"  step {max(r.steps for r in results)}: "
                      f"{sum(1 for v in remaining if v > 0)} running, "

@@ -183,3 +183,17 @@ def test_proposal_edges_of_the_window():
     assert b[0] == lo and b[1] == pytest.approx(lo + TOL, abs=1e-9)       # breaks everywhere
     b = _logistic_surrogate(0.255, 0.001).propose(1.0, 1.0, 0.5, lo, hi, tol=TOL)
     assert b[1] == hi and b[0] == pytest.approx(0.255 - TOL, abs=1e-3)    # clipped at the top
+
+
+def test_still_elongating_reads_the_length_history():
+    h = lambda steps_lp: [(s, 0.0, 45.0, lp, 1) for s, lp in steps_lp]
+    # stretching over the last 4000 steps
+    assert sweep.still_elongating(h([(12000, 140), (14000, 142), (16000, 144)]))
+    # relaxing or holding its length
+    assert not sweep.still_elongating(h([(12000, 98), (14000, 94), (16000, 90)]))
+    assert not sweep.still_elongating(h([(12000, 120), (14000, 120), (16000, 120)]))
+    # compares with the latest check at or before 4000 steps back (11000, not 12500)
+    assert not sweep.still_elongating(h([(11000, 150), (12500, 100), (16000, 110)]))
+    assert sweep.still_elongating(h([(11000, 100), (12500, 150), (16000, 110)]))
+    assert not sweep.still_elongating(h([(13000, 100), (16000, 110)]))      # no check far enough back
+    assert not sweep.still_elongating([])
