@@ -4,7 +4,8 @@ reference.
 
     python -m paper_1411_2181_amd.study generate DATA.json [--runs 160] [--skip 0] [--near D1.json]
     python -m paper_1411_2181_amd.study search OUT.json --data DATA.json[,DATA2.json] \
-        [--queries 32] [--fp64-queries 1] [--precision fp32|fp16s]
+        [--queries 32] [--fp64-queries 1] [--precision fp32|fp16s] [--extend-to N] \
+        [--only I,J,...] [--plain-only]
     python -m paper_1411_2181_amd.study elongation OUT.json --search SEARCH.json [--queries 4]
     python -m paper_1411_2181_amd.study fp64 OUT.json [--queries 4] [--compare SEARCH.json]
     python -m paper_1411_2181_amd.study scan OUT.json --De 1.2 --c 0.63 --fraction 0.2 \
