@@ -32,7 +32,10 @@ Searches: tolerance 0.02 (Ca_cr located within +-0.01), window
 window; the surrogate's search starts from the network's bracket (centred
 where its break-up probability crosses 1/2, at least +-0.02 wide) and falls
 back outward when a bracket end fails (sweep.bisect).  Both advance every query's runs of a round
-as one batch (FP32 or FP16S storage).  The plain FP64 one-run-at-a-time variant is timed on
+as one batch (FP32 or FP16S storage).  A run lasts T_END steps; with
+``--extend-to`` a droplet still stretching at T_END runs on (sweep.simulate),
+which keeps slow binary break-ups just below the onset of ternary break-up
+from being taken as stable.  The plain FP64 one-run-at-a-time variant is timed on
 ``--fp64-queries`` triples.
 """
 from __future__ import annotations
