@@ -197,3 +197,33 @@ def test_still_elongating_reads_the_length_history():
     assert sweep.still_elongating(h([(11000, 100), (12500, 150), (16000, 110)]))
     assert not sweep.still_elongating(h([(13000, 100), (16000, 110)]))      # no check far enough back
     assert not sweep.still_elongating([])
+
+
+def test_scan_report(monkeypatch, tmp_path):
+    import json
+    import types
+    from paper_1411_2181_amd import study
+
+    def fake_simulate(specs, precision, t_end=None, every=500, **kw):
+        out = []
+        for sp in specs:
+            r = sweep.RunResult(sp, dict(nx=4, ny=5, nz=6), dict(tau_em=50.0))
+            br = sp.Ca > 0.2
+            r.history = [(s, 0.1, 45.0, 48.0 + s / 1000.0, 2 if (br and s == 2000) else 1)
+                         for s in range(every, (2000 if br else t_end) + 1, every)]
+            r.broken, r.step_break = br, (2000 if br else -1)
+            r.pieces, r.steps = ([300, 300] if br else []), r.history[-1][0]
+            out.append(r)
+        return out, 1.0
+    monkeypatch.setattr(sweep, "simulate", fake_simulate)
+    out = tmp_path / "scan.json"
+    args = types.SimpleNamespace(out=str(out), De=1.0, c=0.5, fraction=0.2, L2=100.0, R=24.0,
+                                 ca="0.15,0.25", t_end=4000, every=500, precision="fp32")
+    study.cmd_scan(args, lambda m: None)
+    d = json.loads(out.read_text())
+    assert d["lam"] == pytest.approx(1.0) and d["fraction"] == 0.2 and d["t_end"] == 4000
+    stable, broken = d["rows"]
+    assert not stable["broken"] and stable["t_break_over_tau_em"] is None
+    assert broken["broken"] and broken["step_break"] == 2000 and broken["daughter_nodes"] == [300, 300]
+    assert broken["t_break_over_tau_em"] == pytest.approx(40.0)
+    assert stable["Lp_max_over_2R"] == pytest.approx((48.0 + 4.0) / 48.0)
