@@ -365,3 +365,25 @@ def test_full_size_one_step_sampled(lbm, precision, tol):
         print(f"  column ({x}, {y}): f {ef:.1e}, C {eC:.1e}", flush=True)
         assert o.status == 0
         assert ef <= tol and eC <= tol, (x, y, ef, eC)
+
+
+@pytest.mark.parametrize("eta", [(0.0, 0.0), (0.0, 0.05)])
+def test_no_droplet_couette_parity(lbm, eta):
+    # degenerate case: no droplet (R = 0), plane Couette flow of the matrix,
+    # with and without polymer in the matrix
+    d = WL.base_params(nx=8, ny=6, nz=20, radius=0.0, u_wall=0.01, tau=(1.0, 1.0),
+                       tau_P=(1.0, 40.0), eta_P=eta, L2=(100.0, 100.0))
+    print(f"case no droplet, eta_P {eta}", flush=True)
+    s = lbm.Solver(d, "fp64")
+    s.step(300)
+    g = _fields(s)
+    o = Oracle(d)
+    o.step(300)
+    assert rel(g["f"], o.f) <= 1e-12
+    assert rel(g["C"], o.C) <= 1e-12
+    assert rel(g["u"], o.velocity()) <= 1e-11
+    ob = s.observe(components=True)
+    assert ob["status"] == 0 and ob["weight"] == 0.0
+    assert ob["D"] == 0.0 and ob["Lp"] == 0.0
+    assert ob["n_components"] == 0 and ob["piece_nodes"] == [0, 0, 0, 0]
+    s.close()
