@@ -1,0 +1,50 @@
+"""Host-side measurements used by the calibration and the precision study,
+checked on synthetic fields with known answers."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1411_2181_amd import calibrate
+
+
+def _sphere_fields(n, R, rho_in, rho_out):
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    c = n // 2 - 0.5          # centre between the four central nodes the measure averages
+    inside = (x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2 < R * R
+    rA = np.where(inside, rho_in[0], rho_out[0])
+    rB = np.where(inside, rho_in[1], rho_out[1])
+    return np.stack([rA, rB]), int(inside.sum())
+
+
+@pytest.mark.parametrize("R", [8.0, 12.0])
+def test_laplace_measure_on_a_sharp_sphere(R):
+    G = 0.75
+    rho_in, rho_out = (1.0, 0.04), (0.05, 1.02)
+    rho, nodes = _sphere_fields(48, R, rho_in, rho_out)
+    dp, reff = calibrate.laplace_measure(rho, G)
+    P = lambda a, b: (a + b) / 3.0 + G * a * b
+    assert dp == pytest.approx(P(*rho_in) - P(*rho_out), rel=1e-12)
+    # the volume of a sharp sphere is its node count
+    assert reff == pytest.approx((3.0 * nodes / (4.0 * math.pi)) ** (1.0 / 3.0), rel=1e-12)
+    assert reff == pytest.approx(R, rel=0.02)
+
+
+def test_precision_comparison_arithmetic():
+    from paper_1411_2181_amd import precision_study as ps
+    u64 = np.ones((3, 2, 2, 2))
+    u32 = u64.copy()
+    u32[0, 0, 0, 0] += 0.3                       # rel. L2 = 0.3 / sqrt(24)
+
+    def run(D, th, m, m0):
+        return dict(hist=[[dict(step=100, D=D, theta=th, mass=m, status=0)]], u={100: [u32]},
+                    mass0=[m0], seconds=1.0)
+    tw = {"fp64": run(0.20, 40.0, (10.0, 5.0), (10.0, 5.0)),
+          "fp32": run(0.21, 41.5, (10.001, 4.999), (10.0, 5.0))}
+    tw["fp64"]["u"] = {100: [u64]}
+    (row,) = ps.compare(tw, 1)
+    assert row["precision"] == "fp32"
+    assert row["max_dD"] == pytest.approx(0.01) and row["max_dtheta"] == pytest.approx(1.5)
+    assert row["u_rel_l2"][100] == pytest.approx(0.3 / math.sqrt(24.0), rel=1e-12)
+    drift = row["checkpoints"][0]["mass_drift"]
+    assert drift[0] == pytest.approx(1e-4) and drift[1] == pytest.approx(-2e-4)
