@@ -237,7 +237,7 @@ def main():
         v = [int(t) for t in args.launch.lower().split("x")]
         launch = dict(bx=v[0], by=v[1], bz=v[2], persistent=v[3] if len(v) > 3 else 0)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
+        print(json.dumps({"error": "the step runs on one GPU only; "
                                    "multi-GPU slab decomposition is a design note"}))
         sys.exit(2)
     import torch
