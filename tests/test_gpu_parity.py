@@ -387,3 +387,23 @@ def test_no_droplet_couette_parity(lbm, eta):
     assert ob["D"] == 0.0 and ob["Lp"] == 0.0
     assert ob["n_components"] == 0 and ob["piece_nodes"] == [0, 0, 0, 0]
     s.close()
+
+
+def test_layered_couette_parity(lbm):
+    """Polymer layer below a Newtonian layer in plane Couette flow (the
+    stress-balance case of the oracle's polymer pins): FP64 fields after
+    2000 steps against the oracle."""
+    from tests.test_oracle_polymer import layered_couette_params, layered_state
+    d = layered_couette_params(24)
+    f0 = layered_state(24)
+    print("case layered Couette 3x3x24, 2000 steps", flush=True)
+    s = lbm.Solver(d, "fp64")
+    s.import_("f", f0)
+    s.step(2000)
+    g = _fields(s)
+    o = Oracle(d, f=f0)
+    o.step(2000)
+    for k, ref in (("f", o.f), ("C", o.C), ("rho", o.density()), ("u", o.velocity())):
+        assert rel(g[k], ref) <= 1e-10, k
+    assert abs(o.C[4]).max() > 1e-2      # the polymer layer is sheared
+    s.close()
