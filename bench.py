@@ -8,18 +8,19 @@ matrix (L^2 = 400, De = 1, polymer fraction 0.4), viscosity ratio 0.5, wall
 speed 0.1 (Ca = 0.176 at the calibrated surface tension; the work per update
 does not depend on Ca); synthetic
 initial state (sphere at rest, C = I), inputs resident in HBM before the
-timed region.  One step = force pass + collide/stream pass + FENE-P pass
-over every node.  Prints ONE JSON line.
+timed region.  One step = one launch of the step kernel (forces, collision
+and streaming of both components, FENE-P update) over every node.  Prints
+ONE JSON line.
 
 The launch shape is picked by the autotuner before the timed region (or
 pinned with --launch).  After the warm-up steps, one untimed pass of K steps
 instantiates every HIP-graph chunk that a K-step call replays; then five
 regions of K steps each are timed (synchronised on both sides) and the
 median region is reported.  The timed regions replay the library's HIP
-graphs (the production path); the per-pass durations for the roofline come from HIP
-events around each pass in a second region of the same length on the same
-stream.  The roofline is given for the dominant kernel (collide-stream) and
-for the whole step; measured HBM traffic per dispatch comes from the
+graphs (the production path); the kernel duration for the roofline comes
+from HIP events around each step kernel in a further region of the same
+length on the same stream.  The step kernel is the whole step, so its
+roofline is the step's; measured HBM traffic per dispatch comes from the
 committed rocprofv3 counter summary (profiles/traffic_mv512.json) while the
 kernel sources are unchanged.  A 1 GiB device-to-device copy timed in the
 same process gives the measured bandwidth ceiling beside the 8 TB/s peak.
@@ -41,8 +42,11 @@ METRIC = "MLUPS (D3Q19x2 + FENE-P), % HBM roofline; Ca_cr sweeps/hour at +/-0.01
 # algorithmic bytes per lattice update: read and write every population of
 # both components and every conformation component once
 B_ALG = {"fp64": 2 * (38 + 6) * 8, "fp32": 2 * (38 + 6) * 4, "fp16s": 2 * (38 * 2 + 6 * 4)}
-# the populations' share, moved by the collide-stream kernel
-B_ALG_COLLIDE = {"fp64": 2 * 38 * 8, "fp32": 2 * 38 * 4, "fp16s": 2 * 38 * 2}
+# bytes the step kernel must move per update: the algorithmic bytes plus the
+# node densities and momenta (8 values, read and written) that carry the
+# moments between steps
+B_KERNEL = {"fp64": B_ALG["fp64"] + 2 * 8 * 8, "fp32": B_ALG["fp32"] + 2 * 8 * 4,
+            "fp16s": B_ALG["fp16s"] + 2 * 8 * 4}
 REGIONS = 5     # timed regions of K steps; the median is reported
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f16 storage / f32 compute"}
 
@@ -111,12 +115,12 @@ def gpu_run(precision, steps, warmup, launch=None, box=BOX):
         s.step(steps)
         torch.cuda.synchronize()
         regions.append(time.perf_counter() - t0)
-    ms = s.step_profiled(steps)
+    ms = s.step_profiled(steps) / steps
     obs = s.observe()
     launch = s.launch
     s.close()
     wall = sorted(regions)[len(regions) // 2]
-    return dict(nodes=nodes, wall=wall, regions=regions, ms=[m / steps for m in ms], obs=obs, params=p,
+    return dict(nodes=nodes, wall=wall, regions=regions, ms=ms, obs=obs, params=p,
                 info=info, launch=launch, tuned=tuned, box=tuple(box))
 
 
@@ -222,40 +226,30 @@ def cpu_baseline(seconds=12.0):
 
 
 def roofline(precision, r):
-    """Roofline of the dominant kernel (the collide-stream pass, about 60 % of
-    a step) and of the whole step, from the per-pass HIP-event durations."""
+    """Roofline of the step kernel (the whole step in one launch) from its
+    HIP-event duration: algorithmic bytes per update (every population and
+    C component read and written once) over the kernel time."""
     nodes = r["nodes"]
-    ms_force, ms_coll, ms_fene = r["ms"]
-    bc = B_ALG_COLLIDE[precision]
-    ach = bc * nodes / (ms_coll * 1e-3) / 1e9
-    step_ms = ms_force + ms_coll + ms_fene
+    ms = r["ms"]
     balg = B_ALG[precision]
-    step_ach = balg * nodes / (step_ms * 1e-3) / 1e9
+    ach = balg * nodes / (ms * 1e-3) / 1e9
     tr = measured_traffic(precision, r["launch"], r.get("box", BOX))
-    step = {
-        "kernels": "k_force + k_collide + k_fene",
-        "bytes_alg_per_update": balg,
-        "achieved": round(step_ach, 1),
-        "frac": round(step_ach / HBM_PEAK_GBS, 4),
-        "ms_per_pass": {"force": round(ms_force, 4), "collide": round(ms_coll, 4),
-                        "fene": round(ms_fene, 4)},
-        "traffic_per_update": tr["step_bytes_per_node"] if tr else None,
-    }
-    if tr:
-        moved = tr["step_bytes_per_node"] * nodes
-        step["achieved_actual"] = round(moved / (step_ms * 1e-3) / 1e9, 1)
-    return {
+    out = {
         "bound": "hbm",
-        "kernel": "k_collide (collide, stream and bounce-back; both components)",
+        "kernel": "k_step (forces, collide-stream of both components, FENE-P: the whole step)",
         "achieved": round(ach, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(ach / HBM_PEAK_GBS, 4),
-        "traffic": tr["k_collide"]["bytes"] if tr else None,
-        "bytes_alg_per_node": bc,
-        "ms_per_launch": round(ms_coll, 4),
-        "step": step,
+        "traffic": tr["k_step"]["bytes"] if tr else None,
+        "bytes_alg_per_node": balg,
+        "bytes_min_per_node": B_KERNEL[precision],
+        "ms_per_launch": round(ms, 4),
+        "traffic_per_node": tr["k_step"]["bytes_per_node"] if tr else None,
     }
+    if tr:
+        out["achieved_actual"] = round(tr["k_step"]["bytes"] / (ms * 1e-3) / 1e9, 1)
+    return out
 
 
 def main():

@@ -60,9 +60,11 @@ enum {
 enum {
   LBM_FP64 = 0,   /* populations FP64, C FP64, arithmetic FP64                */
   LBM_FP32 = 1,   /* populations FP32, C FP32, arithmetic FP32                */
-  LBM_FP16S = 2   /* populations FP16 stored as f_i - w_i rho_s(x), the
-                     shift taken from the FP32 density of the node holding
-                     the value; C FP32, arithmetic FP32                       */
+  LBM_FP16S = 2   /* populations FP16 stored as
+                     (f_i - w_i (rho_s(x) + 3 c_i.j_s(x))) * 2^12, the shift
+                     taken from the FP32 density and momentum of the node
+                     holding the value and rounded stochastically; densities,
+                     momenta and C FP32, arithmetic FP32                      */
 };
 /* In every precision the Peterlin factor f(tr C) and all observable
  * reductions are evaluated in FP64. */
@@ -128,12 +130,13 @@ typedef struct {
   int32_t status;        /* LBM_OK, LBM_ENAN or LBM_EFENE for this run       */
 } lbm_obs;
 
-/* Launch shape of the step kernels (chosen by the autotuner).  A tile is
- * bx * by columns of nodes advanced by one workgroup of bx * by threads,
- * which marches up bz planes in z; persistent > 0 caps the grid at that many
- * workgroups, which then loop over the tile table. */
+/* Launch shape of the step kernel (chosen by the autotuner).  A tile is
+ * bx * by columns of nodes advanced by two workgroups of bx * by threads
+ * (one per component), which march up bz planes in z; persistent > 0 caps
+ * the grid at that many workgroups (rounded down to a multiple of 16, at
+ * least 16), which then loop over the tile table. */
 typedef struct {
-  int32_t bx, by;        /* (64,4) (32,8) (128,2) (64,2) or (32,4)           */
+  int32_t bx, by;        /* (32,8) (64,4) (16,16), or (32,16) except FP64    */
   int32_t bz;            /* planes per tile, 1 <= bz <= 1024                 */
   int32_t persistent;    /* 0 = one workgroup per tile                        */
 } lbm_launch;
@@ -171,12 +174,13 @@ int lbm_step(lbm_ctx* ctx, int32_t nsteps);
 int lbm_observe(lbm_ctx* ctx, int32_t want_components, lbm_obs* out);
 /* Copy a field of run 0 to / from a host FP64 buffer of n elements (the
  * exact element count of the field, else LBM_EINVAL); synchronises.  Only F
- * and C can be imported.  Populations are held as g_i = f_i - w_i rho_s(x)
- * against the node densities: export of F decodes them in FP64; import of F
- * sets rho_s = sum_i f_i (FP64, rounded to the field type), the shifted
- * values against it and the momenta.  Status is cleared on import.  An F
- * export/import round trip is exact up to that rounding; for a bit-exact
- * restart use lbm_batch_save_state / lbm_batch_load_state. */
+ * and C can be imported.  Populations are held as
+ * g_i = f_i - w_i (rho_s(x) + 3 c_i.j_s(x)) against the node's density and
+ * momentum: export of F decodes them in FP64; import of F sets
+ * rho_s = sum_i f_i and j_s = sum_i c_i f_i (FP64, rounded to the field
+ * type) and the shifted values against them.  Status is cleared on import.
+ * An F export/import round trip is exact up to that rounding; for a
+ * bit-exact restart use lbm_batch_save_state / lbm_batch_load_state. */
 int lbm_export(lbm_ctx* ctx, int32_t field, double* host, size_t n);
 int lbm_import(lbm_ctx* ctx, int32_t field, const double* host, size_t n);
 void lbm_destroy(lbm_ctx* ctx);
@@ -185,10 +189,9 @@ void lbm_destroy(lbm_ctx* ctx);
 int lbm_get_launch(const lbm_ctx* ctx, lbm_launch* out);
 int lbm_set_launch(lbm_ctx* ctx, const lbm_launch* in);
 /* Advance every run by nsteps with eager launches and HIP events around
- * each pass; ms_pass[0..2] receive the summed durations of the force pass,
- * the collide-stream pass and the FENE-P pass (for roofline accounting).
- * Synchronises. */
-int lbm_step_profiled(lbm_ctx* ctx, int32_t nsteps, double* ms_pass);
+ * each launch of the step kernel; *ms_step receives the summed kernel
+ * durations in milliseconds (for roofline accounting).  Synchronises. */
+int lbm_step_profiled(lbm_ctx* ctx, int32_t nsteps, double* ms_step);
 /* Steps actually taken by run r since init. */
 int lbm_steps_done(const lbm_ctx* ctx, int32_t run, int64_t* out);
 
@@ -214,11 +217,11 @@ int lbm_batch_import(lbm_ctx* ctx, int32_t run, int32_t field,
 int32_t lbm_batch_nruns(const lbm_ctx* ctx);
 
 /* ---- checkpoint / restart ------------------------------------------------
- * The raw state of one run: populations as stored, node densities and C,
- * behind a header (precision, box, viscoelastic phase, step count).  A load
- * restores the run bit for bit, including its step count, into a context of
- * the same precision whose run has the same box and viscoelastic phase
- * (else LBM_EINVAL); it recomputes the momenta and clears the run's status.
+ * The raw state of one run: populations as stored, node densities, momenta
+ * and C, behind a header (precision, box, viscoelastic phase, step count).
+ * A load restores the run bit for bit, including its step count, into a
+ * context of the same precision whose run has the same box and viscoelastic
+ * phase (else LBM_EINVAL), and clears the run's status.
  * The host buffer is the caller's; bytes must equal lbm_batch_state_bytes.
  * Both synchronise the context's stream. */
 int lbm_batch_state_bytes(const lbm_ctx* ctx, int32_t run, size_t* bytes);

@@ -16,14 +16,16 @@ import time
 _HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(_HERE, "autotune_cache.json")
 
-SHAPES = [(64, 4), (32, 8), (128, 2), (64, 2), (32, 4)]
+SHAPES = [(32, 8), (64, 4), (16, 16), (32, 16)]
 BZ = [8, 16, 32, 64]
 PERSISTENT = [1024, 2048]
 
 
-def candidates(nz_max: int):
+def candidates(nz_max: int, precision: str = "fp32"):
+    # the FP64 rings of the 512-thread tile exceed the LDS
+    shapes = [sh for sh in SHAPES if not (precision == "fp64" and sh == (32, 16))]
     out = []
-    for bx, by in SHAPES:
+    for bx, by in shapes:
         for bz in BZ:
             if bz <= max(8, nz_max):
                 out.append(dict(bx=bx, by=by, bz=bz, persistent=0))
@@ -62,12 +64,12 @@ def tune(batch, steps: int = 4, cands=None, use_cache: bool = True, save: bool =
         batch.set_launch(**cache[key]["launch"])
         return dict(cache[key], cached=True)
     nz_max = max(d["nz"] for d in batch.dicts)
-    cands = cands or candidates(nz_max)
+    cands = cands or candidates(nz_max, batch.precision)
     table = []
     batch.step_profiled(steps)          # warm-up: graph-free, first-touch
     for c in cands:
         batch.set_launch(**c)
-        ms = sum(batch.step_profiled(steps)) / steps
+        ms = batch.step_profiled(steps) / steps
         table.append(dict(launch=c, ms_per_step=ms))
     best = min(table, key=lambda r: r["ms_per_step"])
     # persistent grids of the best shape (a few workgroups per CU looping over
@@ -75,7 +77,7 @@ def tune(batch, steps: int = 4, cands=None, use_cache: bool = True, save: bool =
     for pers in (PERSISTENT if persistent else []):
         c = dict(best["launch"], persistent=pers)
         batch.set_launch(**c)
-        ms = sum(batch.step_profiled(steps)) / steps
+        ms = batch.step_profiled(steps) / steps
         table.append(dict(launch=c, ms_per_step=ms))
     best = min(table, key=lambda r: r["ms_per_step"])
     batch.set_launch(**best["launch"])

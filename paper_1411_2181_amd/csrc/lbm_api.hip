@@ -58,7 +58,7 @@ bool coexistence(double G, double rho_tot, double* lo, double* hi) {
 }
 
 struct Layout {
-  size_t f[2], rho[2], j[2], C[2], recA, recB, u, labels, counts, status, ncomp, pieces, gstep,
+  size_t f[2], rho[2], j[2], C[2], u, labels, counts, status, ncomp, pieces, gstep,
       runs, tiles, partials, obs, rc, rinit, total;
   int64_t tiles_cap;
 };
@@ -90,8 +90,6 @@ Layout make_layout(const lbm_params* p, int32_t nruns) {
   for (int b = 0; b < 2; ++b) L.rho[b] = take((size_t)nodes * 2 * t);
   for (int b = 0; b < 2; ++b) L.j[b] = take((size_t)nodes * 6 * t);
   for (int b = 0; b < 2; ++b) L.C[b] = take((size_t)nodes * 6 * t);
-  L.recA = take((size_t)nodes * 4 * t);
-  L.recB = take((size_t)nodes * 4 * t);
   L.u = take((size_t)nodes * 3 * t);
   L.labels = take((size_t)nodes * 4);
   L.counts = take((size_t)nodes * 4);
@@ -115,15 +113,13 @@ Layout make_layout(const lbm_params* p, int32_t nruns) {
 struct lbm_ctx {
   int32_t nruns = 0, prec = 0;
   hipStream_t stream = nullptr;
-  hipStream_t cap = nullptr;    // private streams used only to capture graphs
-  hipStream_t cap2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t cap = nullptr;    // private stream used only to capture graphs
   std::vector<lbm_params> prm;
   std::vector<RunDev> runs;
   std::vector<int64_t> done;
   char* ws = nullptr;
   Layout L{};
-  lbm_launch launch{64, 4, 16, 0};
+  lbm_launch launch{32, 8, 16, 0};
   int64_t ntiles = 0;          // entries of the (XCD-permuted) tile table
   std::map<int, hipGraphExec_t> graphs;
   std::map<int, hipGraph_t> graph_src;
@@ -143,8 +139,6 @@ lbm::Pools<T, S> pools(const lbm_ctx* c) {
     P.j[b] = c->at<T>(c->L.j[b]);
     P.C[b] = c->at<T>(c->L.C[b]);
   }
-  P.recA = c->at<lbm::V4<T>>(c->L.recA);
-  P.recB = c->at<lbm::V4<T>>(c->L.recB);
   P.u = c->at<T>(c->L.u);
   P.status = c->at<uint32_t>(c->L.status);
   return P;
@@ -182,9 +176,12 @@ lbm::AuxArgs<T, S> aux_args(const lbm_ctx* c, int use_parity) {
   return a;
 }
 
+// Two workgroups per tile slot (one per component, 8 ids apart so that both
+// run on the same XCD); a persistent grid is a multiple of 16 workgroups
+// that loop over the tile table.
 dim3 step_grid(const lbm_ctx* c) {
-  int64_t g = c->ntiles;
-  if (c->launch.persistent > 0) g = std::min<int64_t>(g, std::max(8, c->launch.persistent / 8 * 8));
+  int64_t g = 2 * c->ntiles;
+  if (c->launch.persistent > 0) g = std::min<int64_t>(g, std::max(16, c->launch.persistent / 16 * 16));
   return dim3((unsigned)g);
 }
 
@@ -335,36 +332,13 @@ int set_targets(lbm_ctx* c, const int32_t* target) {
   return hip_ok(hipGetLastError());
 }
 
-void enqueue_force(lbm_ctx* c, hipStream_t s) {
+// One step: the fused step kernel, then the step counter.
+void enqueue_step(lbm_ctx* c, hipStream_t s) {
   const dim3 grid = step_grid(c), block(c->launch.bx, c->launch.by);
   by_precision(c->prec, [&](auto* tt, auto* ss) {
     using T = std::remove_pointer_t<decltype(tt)>;
     using S = std::remove_pointer_t<decltype(ss)>;
-    lbm::launch_force<T, S>(step_args<T, S>(c), grid, block, s);
-  });
-}
-
-// One step.  With a side stream (graph capture) the FENE-P pass forks off
-// after the force pass and runs concurrently with the collide pass: both read
-// only state n and the force-pass outputs and write disjoint fields.
-void enqueue_step(lbm_ctx* c, hipStream_t s, hipStream_t side) {
-  const dim3 grid = step_grid(c), block(c->launch.bx, c->launch.by);
-  by_precision(c->prec, [&](auto* tt, auto* ss) {
-    using T = std::remove_pointer_t<decltype(tt)>;
-    using S = std::remove_pointer_t<decltype(ss)>;
-    const auto a = step_args<T, S>(c);
-    lbm::launch_force<T, S>(a, grid, block, s);
-    if (side && a.any_visc) {
-      hipEventRecord(c->ev_fork, s);
-      hipStreamWaitEvent(side, c->ev_fork, 0);
-      lbm::launch_fene<T, S>(a, grid, block, side);
-      lbm::launch_collide<T, S>(a, grid, block, s);
-      hipEventRecord(c->ev_join, side);
-      hipStreamWaitEvent(s, c->ev_join, 0);
-    } else {
-      lbm::launch_collide<T, S>(a, grid, block, s);
-      lbm::launch_fene<T, S>(a, grid, block, s);
-    }
+    lbm::launch_step<T, S>(step_args<T, S>(c), grid, block, s);
   });
   lbm::launch_inc_step(c->at<int32_t>(c->L.gstep), s);
 }
@@ -373,12 +347,9 @@ int get_graph(lbm_ctx* c, int chunk, hipGraphExec_t* out) {
   auto it = c->graphs.find(chunk);
   if (it != c->graphs.end()) { *out = it->second; return LBM_OK; }
   if (!c->cap) HIPCHK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
-  if (!c->cap2) HIPCHK(hipStreamCreateWithFlags(&c->cap2, hipStreamNonBlocking));
-  if (!c->ev_fork) HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-  if (!c->ev_join) HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-  for (int k = 0; k < chunk; ++k) enqueue_step(c, c->cap, c->cap2);
+  for (int k = 0; k < chunk; ++k) enqueue_step(c, c->cap);
   const hipError_t e = hipStreamEndCapture(c->cap, &g);
   if (e != hipSuccess || !g) return LBM_EHIP;
   hipGraphExec_t ex = nullptr;
@@ -415,12 +386,16 @@ int run_steps(lbm_ctx* c, const int32_t* target) {
   return LBM_OK;
 }
 
-// Force pass on the current state of every run (fills u^eq and u).
+// Physical velocity of every run at its current state (observe, export).
 int refresh_flow(lbm_ctx* c) {
-  std::vector<int32_t> one(c->nruns, 1);
-  const int e = set_targets(c, one.data());
+  std::vector<int32_t> zero(c->nruns, 0);
+  const int e = set_targets(c, zero.data());
   if (e) return e;
-  enqueue_force(c, c->stream);
+  by_precision(c->prec, [&](auto* tt, auto* ss) {
+    using T = std::remove_pointer_t<decltype(tt)>;
+    using S = std::remove_pointer_t<decltype(ss)>;
+    lbm::launch_flow<T, S>(aux_args<T, S>(c, 1), c->stream);
+  });
   return hip_ok(hipGetLastError());
 }
 
@@ -533,9 +508,7 @@ int lbm_batch_init(const lbm_params* runs, int32_t nruns, void* ws, size_t bytes
   by_precision(c->prec, [&](auto* tt, auto* ss) {
     using T = std::remove_pointer_t<decltype(tt)>;
     using S = std::remove_pointer_t<decltype(ss)>;
-    const auto a = aux_args<T, S>(c, 0);
-    lbm::launch_init<T, S>(a, c->stream);
-    lbm::launch_moments<T, S>(a, c->stream);
+    lbm::launch_init<T, S>(aux_args<T, S>(c, 0), c->stream);
   });
   if (hipGetLastError() != hipSuccess) return fail(LBM_EHIP);
   *out = c;
@@ -551,9 +524,6 @@ void lbm_destroy(lbm_ctx* c) {
   if (c->stream || c->cap) hipStreamSynchronize(c->stream);
   destroy_graphs(c);
   if (c->cap) hipStreamDestroy(c->cap);
-  if (c->cap2) hipStreamDestroy(c->cap2);
-  if (c->ev_fork) hipEventDestroy(c->ev_fork);
-  if (c->ev_join) hipEventDestroy(c->ev_join);
   delete c;
 }
 
@@ -568,10 +538,8 @@ int lbm_get_launch(const lbm_ctx* c, lbm_launch* out) {
 int lbm_set_launch(lbm_ctx* c, const lbm_launch* in) {
   if (!c || !in) return LBM_EINVAL;
   const lbm_launch l = *in;
-  // block shapes with a compiled update-pass instance
-  const bool shape_ok = (l.bx == 64 && l.by == 4) || (l.bx == 32 && l.by == 8) ||
-                        (l.bx == 128 && l.by == 2) || (l.bx == 64 && l.by == 2) ||
-                        (l.bx == 32 && l.by == 4);
+  // block shapes with a compiled step-kernel instance for this precision
+  const bool shape_ok = lbm::step_shape_ok(l.bx, l.by, c->prec == LBM_FP64);
   if (!shape_ok || l.bz < 1 || l.bz > 1024 || l.persistent < 0) return LBM_EINVAL;
   const lbm_launch old = c->launch;
   c->launch = l;
@@ -591,14 +559,14 @@ int lbm_batch_step(lbm_ctx* c, const int32_t* steps) {
   return run_steps(c, steps);
 }
 
-int lbm_step_profiled(lbm_ctx* c, int32_t nsteps, double* ms_pass) {
-  if (!c || nsteps < 0 || !ms_pass) return LBM_EINVAL;
-  ms_pass[0] = ms_pass[1] = ms_pass[2] = 0.0;
+int lbm_step_profiled(lbm_ctx* c, int32_t nsteps, double* ms_step) {
+  if (!c || nsteps < 0 || !ms_step) return LBM_EINVAL;
+  *ms_step = 0.0;
   if (nsteps == 0) return LBM_OK;
   std::vector<int32_t> t(c->nruns, nsteps);
   int e = set_targets(c, t.data());
   if (e) return e;
-  std::vector<hipEvent_t> ev(4 * (size_t)nsteps, nullptr);
+  std::vector<hipEvent_t> ev(2 * (size_t)nsteps, nullptr);
   for (auto& x : ev)
     if (hipEventCreate(&x) != hipSuccess) { e = LBM_EHIP; break; }
   const dim3 grid = step_grid(c), block(c->launch.bx, c->launch.by);
@@ -606,24 +574,17 @@ int lbm_step_profiled(lbm_ctx* c, int32_t nsteps, double* ms_pass) {
     by_precision(c->prec, [&](auto* tt, auto* ss) {
       using T = std::remove_pointer_t<decltype(tt)>;
       using S = std::remove_pointer_t<decltype(ss)>;
-      const auto a = step_args<T, S>(c);
-      hipEventRecord(ev[4 * k], c->stream);
-      lbm::launch_force<T, S>(a, grid, block, c->stream);
-      hipEventRecord(ev[4 * k + 1], c->stream);
-      lbm::launch_collide<T, S>(a, grid, block, c->stream);
-      hipEventRecord(ev[4 * k + 2], c->stream);
-      lbm::launch_fene<T, S>(a, grid, block, c->stream);
-      hipEventRecord(ev[4 * k + 3], c->stream);
+      hipEventRecord(ev[2 * k], c->stream);
+      lbm::launch_step<T, S>(step_args<T, S>(c), grid, block, c->stream);
+      hipEventRecord(ev[2 * k + 1], c->stream);
     });
     lbm::launch_inc_step(c->at<int32_t>(c->L.gstep), c->stream);
   }
   if (!e && hipStreamSynchronize(c->stream) != hipSuccess) e = LBM_EHIP;
   for (int k = 0; k < nsteps && !e; ++k) {
-    for (int p = 0; p < 3; ++p) {
-      float v = 0.f;
-      if (hipEventElapsedTime(&v, ev[4 * k + p], ev[4 * k + p + 1]) != hipSuccess) { e = LBM_EHIP; break; }
-      ms_pass[p] += v;
-    }
+    float v = 0.f;
+    if (hipEventElapsedTime(&v, ev[2 * k], ev[2 * k + 1]) != hipSuccess) { e = LBM_EHIP; break; }
+    *ms_step += v;
   }
   for (auto& x : ev)
     if (x) hipEventDestroy(x);
@@ -730,33 +691,32 @@ int copy_in(lbm_ctx* c, size_t dev_off, size_t elem, int comps, const RunDev& R,
                      hipMemcpyHostToDevice) == hipSuccess ? LBM_OK : LBM_EHIP;
 }
 
-// Momenta of every run at its current parity; clear one run's status.
+// Clear one run's status after its state was replaced.
 int after_state_change(lbm_ctx* c, int run) {
-  std::vector<int32_t> zero(c->nruns, 0);
-  int e = set_targets(c, zero.data());
-  if (e) return e;
-  by_precision(c->prec, [&](auto* ttag, auto* stag) {
-    using T = std::remove_pointer_t<decltype(ttag)>;
-    using S = std::remove_pointer_t<decltype(stag)>;
-    lbm::launch_moments<T, S>(aux_args<T, S>(c, 1), c->stream);
-  });
   lbm::launch_fill_u32(c->at<uint32_t>(c->L.status) + run, 0u, 1, c->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
 
-// Raw state blob: header, then populations as stored, densities and C.
+// Raw state blob: header, then populations as stored, densities, momenta
+// and C.
 struct StateHeader {
   uint64_t magic;
   int32_t precision, nx, ny, nz, visc, pad;
   int64_t done;
 };
-constexpr uint64_t STATE_MAGIC = 0x31534d564d424cull;   // "LBMVMS1"
+constexpr uint64_t STATE_MAGIC = 0x32534d564d424cull;   // "LBMVMS2"
 
 size_t state_bytes(const lbm_ctx* c, int run) {
   const int64_t N = c->runs[run].n;
-  return sizeof(StateHeader) + (size_t)N * (38 * elem_S(c->prec) + 8 * elem_T(c->prec));
+  return sizeof(StateHeader) + (size_t)N * (38 * elem_S(c->prec) + 14 * elem_T(c->prec));
+}
+
+// Shift of direction i against the node moments: w_i (rho + 3 c_i.j).
+double pop_shift(int i, double rho, double jx, double jy, double jz) {
+  return lbm::wgt<double>(i) *
+         (rho + 3.0 * (lbm::CX[i] * jx + lbm::CY[i] * jy + lbm::CZ[i] * jz));
 }
 
 }  // namespace
@@ -779,17 +739,22 @@ int lbm_batch_export(lbm_ctx* c, int32_t run, int32_t field, double* host, size_
   std::vector<char> buf;
   int e = LBM_OK;
   if (field == LBM_FIELD_F) {
-    // f_i = g_i + w_i rho_s(x), decoded in FP64
-    std::vector<char> rb((size_t)2 * N * tt);
+    // f_i = g_i + w_i (rho_s + 3 c_i.j_s), decoded in FP64
+    std::vector<char> rb((size_t)2 * N * tt), jb((size_t)6 * N * tt);
     buf.resize((size_t)want * st);
     e = copy_out(c, c->L.f[par] + (size_t)R.off * 38 * st, st, 38, R, buf.data());
     if (!e) e = copy_out(c, c->L.rho[par] + (size_t)R.off * 2 * tt, tt, 2, R, rb.data());
+    if (!e) e = copy_out(c, c->L.j[par] + (size_t)R.off * 6 * tt, tt, 6, R, jb.data());
     if (e) return e;
     const double isc = 1.0 / pop_scale(c->prec);
     for (int64_t k = 0; k < want; ++k) {
       const int s = (int)(k / (19 * N)), i = (int)((k / N) % 19);
+      const int64_t m = k % N;
       host[k] = get_elem(st, buf.data(), k) * isc +
-                lbm::wgt<double>(i) * get_elem(tt, rb.data(), s * N + k % N);
+                pop_shift(i, get_elem(tt, rb.data(), s * N + m),
+                          get_elem(tt, jb.data(), (3 * s) * N + m),
+                          get_elem(tt, jb.data(), (3 * s + 1) * N + m),
+                          get_elem(tt, jb.data(), (3 * s + 2) * N + m));
     }
     return LBM_OK;
   }
@@ -822,24 +787,39 @@ int lbm_batch_import(lbm_ctx* c, int32_t run, int32_t field, const double* host,
   std::vector<char> buf;
   int e = LBM_OK;
   if (field == LBM_FIELD_F) {
-    // node densities rho_s = sum_i f_i (FP64, rounded to the field type), then
-    // the shifted values g_i = f_i - w_i rho_s against them
-    std::vector<char> rb((size_t)2 * N * tt);
+    // node moments rho_s = sum_i f_i, j_s = sum_i c_i f_i (FP64, rounded to
+    // the field type), then the shifted values g_i = f_i - w_i (rho + 3 c_i.j)
+    // against the rounded moments
+    std::vector<char> rb((size_t)2 * N * tt), jb((size_t)6 * N * tt);
     for (int s = 0; s < 2; ++s)
       for (int64_t m = 0; m < N; ++m) {
-        double r = 0.0;
-        for (int i = 0; i < 19; ++i) r += host[((int64_t)s * 19 + i) * N + m];
+        double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+        for (int i = 0; i < 19; ++i) {
+          const double v = host[((int64_t)s * 19 + i) * N + m];
+          r += v;
+          jx += lbm::CX[i] * v;
+          jy += lbm::CY[i] * v;
+          jz += lbm::CZ[i] * v;
+        }
         put_elem(tt, rb.data(), s * N + m, r);
+        put_elem(tt, jb.data(), (3 * s) * N + m, jx);
+        put_elem(tt, jb.data(), (3 * s + 1) * N + m, jy);
+        put_elem(tt, jb.data(), (3 * s + 2) * N + m, jz);
       }
     buf.resize((size_t)want * st);
     const double sc = pop_scale(c->prec);
     for (int64_t k = 0; k < want; ++k) {
       const int s = (int)(k / (19 * N)), i = (int)((k / N) % 19);
-      put_elem(st, buf.data(), k,
-               (host[k] - lbm::wgt<double>(i) * get_elem(tt, rb.data(), s * N + k % N)) * sc);
+      const int64_t m = k % N;
+      const double sh = pop_shift(i, get_elem(tt, rb.data(), s * N + m),
+                                  get_elem(tt, jb.data(), (3 * s) * N + m),
+                                  get_elem(tt, jb.data(), (3 * s + 1) * N + m),
+                                  get_elem(tt, jb.data(), (3 * s + 2) * N + m));
+      put_elem(st, buf.data(), k, (host[k] - sh) * sc);
     }
     e = copy_in(c, c->L.f[par] + (size_t)R.off * 38 * st, st, 38, R, buf.data());
     if (!e) e = copy_in(c, c->L.rho[par] + (size_t)R.off * 2 * tt, tt, 2, R, rb.data());
+    if (!e) e = copy_in(c, c->L.j[par] + (size_t)R.off * 6 * tt, tt, 6, R, jb.data());
   } else {
     buf.resize((size_t)want * tt);
     for (int64_t k = 0; k < want; ++k) put_elem(tt, buf.data(), k, host[k]);
@@ -872,6 +852,8 @@ int lbm_batch_save_state(lbm_ctx* c, int32_t run, void* host, size_t bytes) {
   q += (size_t)R.n * 38 * st;
   if (!e) e = copy_out(c, c->L.rho[par] + (size_t)R.off * 2 * tt, tt, 2, R, q);
   q += (size_t)R.n * 2 * tt;
+  if (!e) e = copy_out(c, c->L.j[par] + (size_t)R.off * 6 * tt, tt, 6, R, q);
+  q += (size_t)R.n * 6 * tt;
   const int cp = R.visc >= 0 ? par : 0;
   if (!e) e = copy_out(c, c->L.C[cp] + (size_t)R.off * 6 * tt, tt, 6, R, q);
   return e;
@@ -895,6 +877,8 @@ int lbm_batch_load_state(lbm_ctx* c, int32_t run, const void* host, size_t bytes
   q += (size_t)R.n * 38 * st;
   if (!e) e = copy_in(c, c->L.rho[par] + (size_t)R.off * 2 * tt, tt, 2, R, q);
   q += (size_t)R.n * 2 * tt;
+  if (!e) e = copy_in(c, c->L.j[par] + (size_t)R.off * 6 * tt, tt, 6, R, q);
+  q += (size_t)R.n * 6 * tt;
   const int cp = R.visc >= 0 ? par : 0;
   if (!e) e = copy_in(c, c->L.C[cp] + (size_t)R.off * 6 * tt, tt, 6, R, q);
   if (e) return e;

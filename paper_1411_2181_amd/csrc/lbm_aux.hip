@@ -1,5 +1,5 @@
-// Per-node auxiliary kernels: initial state, moments after an import,
-// observable reductions and connected-component labelling of the droplet.
+// Per-node auxiliary kernels: initial state, observable reductions and
+// connected-component labelling of the droplet.
 //
 // All kernels use a (AUX_BLOCKS, nruns) grid: block b of run r owns the
 // contiguous node range [b*chunk, (b+1)*chunk) of that run.  Reductions are
@@ -18,8 +18,8 @@ __device__ __forceinline__ void node_range(int64_t N, int64_t& beg, int64_t& end
 // ---- initial state ----------------------------------------------------------
 // Sphere |x - c|^2 < R^2 (strict) holds rho_A = rho_major, rho_B = rho_minor,
 // the rest the reverse (Section 3: a spherical droplet at mid-gap, shear
-// started from rest); f = w_i rho_s, i.e. the shifted value g_i = 0 against
-// the node density rho_s; C = I.  Written at parity 0.
+// started from rest); f = w_i rho_s, i.e. zero momentum and the shifted
+// value g_i = 0 against the node's moments; C = I.  Written at parity 0.
 template <typename T, typename S>
 __global__ void k_init(AuxArgs<T, S> a) {
   const int r = blockIdx.y;
@@ -33,6 +33,7 @@ __global__ void k_init(AuxArgs<T, S> a) {
   using St = Store<T, S>;
   S* f = a.P.f[0] + 38 * R.off;
   T* rho = a.P.rho[0] + 2 * R.off;
+  T* J = a.P.j[0] + 6 * R.off;
   T* C = a.P.C[0] + 6 * R.off;
   for (int64_t n = beg + threadIdx.x; n < end; n += blockDim.x) {
     const int x = (int)(n % R.nx);
@@ -45,42 +46,12 @@ __global__ void k_init(AuxArgs<T, S> a) {
     for (int s = 0; s < 2; ++s) {
       rho[s * N + n] = T(rho_s[s]);
 #pragma unroll
+      for (int c = 0; c < 3; ++c) J[(3 * s + c) * N + n] = T(0);
+#pragma unroll
       for (int i = 0; i < Q; ++i) St::store(f + ((int64_t)s * Q + i) * N, n, T(0));
     }
 #pragma unroll
     for (int k = 0; k < 6; ++k) C[k * N + n] = k < 3 ? T(1) : T(0);
-  }
-}
-
-// ---- momenta j_s from the stored populations ------------------------------------
-// j_s = sum_i c_i f_i = sum_i c_i g_i (the rest parts w_i rho_s cancel).  The
-// densities are part of the encoding of the populations and stay as they are.
-template <typename T, typename S>
-__global__ void k_moments(AuxArgs<T, S> a) {
-  const int r = blockIdx.y;
-  const RunDev& R = a.runs[r];
-  const int par = a.use_parity ? (R.base & 1) : 0;
-  const int64_t N = R.ld;   // stride between the component arrays of a field
-  int64_t beg, end;
-  node_range(R.n, beg, end);
-  const S* f = a.P.f[par] + 38 * R.off;
-  T* J = a.P.j[par] + 6 * R.off;
-  for (int64_t n = beg + threadIdx.x; n < end; n += blockDim.x) {
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      T jx = 0, jy = 0, jz = 0;
-#pragma unroll
-      for (int i = 1; i < Q; ++i) {
-        const T v = Store<T, S>::load(f + ((int64_t)s * Q + i) * N, n);
-        if (CX[i] != 0) jx += T(CX[i]) * v;
-        if (CY[i] != 0) jy += T(CY[i]) * v;
-        if (CZ[i] != 0) jz += T(CZ[i]) * v;
-      }
-      const T ikS = T(1.0 / Store<T, S>::kScale);
-      J[(3 * s) * N + n] = jx * ikS;
-      J[(3 * s + 1) * N + n] = jy * ikS;
-      J[(3 * s + 2) * N + n] = jz * ikS;
-    }
   }
 }
 
@@ -314,10 +285,6 @@ void launch_init(const AuxArgs<T, S>& a, hipStream_t s) {
   k_init<T, S><<<dim3(AUX_BLOCKS, a.nruns), AUX_THREADS, 0, s>>>(a);
 }
 template <typename T, typename S>
-void launch_moments(const AuxArgs<T, S>& a, hipStream_t s) {
-  k_moments<T, S><<<dim3(AUX_BLOCKS, a.nruns), AUX_THREADS, 0, s>>>(a);
-}
-template <typename T, typename S>
 void launch_observe(const AuxArgs<T, S>& a, hipStream_t s) {
   k_obs_partial<T, S><<<dim3(AUX_BLOCKS, a.nruns), AUX_THREADS, 0, s>>>(a);
   k_obs_final<T, S><<<a.nruns, 64, 0, s>>>(a, AUX_BLOCKS);
@@ -333,7 +300,6 @@ void launch_components(const AuxArgs<T, S>& a, hipStream_t s) {
 
 #define LBM_INST(T, S)                                                   \
   template void launch_init<T, S>(const AuxArgs<T, S>&, hipStream_t);     \
-  template void launch_moments<T, S>(const AuxArgs<T, S>&, hipStream_t);  \
   template void launch_observe<T, S>(const AuxArgs<T, S>&, hipStream_t);  \
   template void launch_components<T, S>(const AuxArgs<T, S>&, hipStream_t);
 LBM_INST(double, double)

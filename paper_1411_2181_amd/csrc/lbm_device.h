@@ -57,15 +57,16 @@ struct Tile {
 };
 
 // ---- storage conversions -------------------------------------------------
-// Populations are stored shifted: g_i = f_i - w_i rho_s(x), x the node that
-// holds the value and rho_s(x) the density array of the same parity (the
-// node's density).  Near equilibrium g_i is small, so rounding acts on the
-// deviation from equilibrium rather than on f itself: this is what lets
-// FP16 (11 significant bits) resolve both phases, and it cuts FP32/FP64
-// rounding of the stored state by the same factor.  Stored as S, in units of
-// 1/kScale (FP16 keeps g * 2^12, which moves the small deviations of the
-// minority phase out of the subnormal range; |g| < 1 stays far below the
-// FP16 maximum), arithmetic in T.  The time step rounds FP16 values
+// Populations are stored shifted by the first two moments of the node that
+// holds them: g_i = f_i - w_i (rho_s(x) + 3 c_i.j_s(x)), with rho_s(x) and
+// j_s(x) the density and momentum arrays of the same parity.  The shift is
+// the equilibrium up to first order in the velocity, so g_i holds only the
+// second-order and non-equilibrium parts: small values, whose rounding (FP16
+// keeps 11 significant bits) is small against the flow.  The moments
+// themselves are carried by the rho / j arrays in the compute type.  Stored
+// as S in units of 1/kScale (FP16 keeps g * 2^12, which moves the small
+// values of the minority phase out of the subnormal range; |g| < 1 stays far
+// below the FP16 maximum), arithmetic in T.  The time step rounds FP16 values
 // stochastically (put); set-up and import round to nearest even (store).
 template <typename T, typename S>
 struct Store;
@@ -91,14 +92,13 @@ struct Store<T, T> {
   static constexpr bool kRandom = false;
   static constexpr double kScale = 1.0;
   static __device__ __forceinline__ T load(const T* p, int64_t k) { return p[k]; }
-  // store v; returns the value as stored (r: random bits, unused here)
-  static __device__ __forceinline__ T put(T* p, int64_t k, T v, uint32_t /*r*/) {
+  // store v (r: random word, unused here)
+  static __device__ __forceinline__ void put(T* p, int64_t k, T v, uint32_t /*r*/) {
 #if LBM_NT_STORES
     __builtin_nontemporal_store(v, p + k);
 #else
     p[k] = v;
 #endif
-    return v;
   }
   static __device__ __forceinline__ void store(T* p, int64_t k, T v) { put(p, k, v, 0u); }
 };
@@ -107,6 +107,8 @@ struct Store<T, T> {
 #define LBM_FP16_RN 0   // 1: round to nearest even instead of stochastically
 #endif
 
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
 template <>
 struct Store<float, __half> {
   static constexpr bool kRandom = !LBM_FP16_RN;
@@ -114,34 +116,30 @@ struct Store<float, __half> {
   static __device__ __forceinline__ float load(const __half* p, int64_t k) {
     return __half2float(p[k]);
   }
-  static __device__ __forceinline__ void raw_store(__half* p, int64_t k, __half h) {
+  static __device__ __forceinline__ void raw_store(__half* p, int64_t k, unsigned short h) {
 #if LBM_NT_STORES
-    __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, h),
-                                reinterpret_cast<unsigned short*>(p) + k);
+    __builtin_nontemporal_store(h, reinterpret_cast<unsigned short*>(p) + k);
 #else
-    p[k] = h;
+    reinterpret_cast<unsigned short*>(p)[k] = h;
 #endif
   }
-  // Stochastic rounding to FP16 with 13 random bits r (r < 2^13): adding r
-  // to the 13 float mantissa bits that FP16 drops and then truncating them
-  // rounds |v| up with probability (|v| - lower)/spacing, so the rounding
-  // error has zero mean.  Deterministic rounding leaves the same error at
-  // every node of a uniform region, step after step, and that coherent bias
-  // accumulates in the flow.  The truncated value is an FP16 number in the
-  // normal range, so the final conversion is exact.
-  static __device__ __forceinline__ float put(__half* p, int64_t k, float v, uint32_t r) {
+  // Stochastic rounding to FP16 with the random word r: gfx950's conversion
+  // adds the top 13 bits of r to the 13 mantissa bits of |v| that FP16 drops
+  // and truncates them, so |v| rounds up with probability
+  // (|v| - lower)/spacing and the rounding error has zero mean.
+  // Deterministic rounding leaves the same error at every node of a uniform
+  // region, step after step, and that coherent bias accumulates in the flow.
+  static __device__ __forceinline__ void put(__half* p, int64_t k, float v, uint32_t r) {
 #if LBM_FP16_RN
     (void)r;
-    const __half h = __float2half_rn(v);
+    raw_store(p, k, __builtin_bit_cast(unsigned short, __float2half_rn(v)));
 #else
-    const uint32_t b = (__float_as_uint(v) + r) & 0xffffe000u;
-    const __half h = __float2half_rn(__uint_as_float(b));
+    const half2v h = __builtin_amdgcn_cvt_sr_f16_f32(half2v{0, 0}, v, r, false);
+    raw_store(p, k, __builtin_bit_cast(unsigned short, h[0]));
 #endif
-    raw_store(p, k, h);
-    return __half2float(h);
   }
   static __device__ __forceinline__ void store(__half* p, int64_t k, float v) {
-    raw_store(p, k, __float2half_rn(v));
+    raw_store(p, k, __builtin_bit_cast(unsigned short, __float2half_rn(v)));
   }
 };
 
@@ -152,9 +150,7 @@ struct Pools {
   T* rho[2];          // [2][n] per run: rho_A, rho_B
   T* j[2];            // [6][n] per run: j_A xyz, j_B xyz
   T* C[2];            // [6][n] per run: xx yy zz xy xz yz
-  V4<T>* recA;        // (rho_A, u^eq_A) per node, written by the force pass
-  V4<T>* recB;        // (rho_B, u^eq_B)
-  T* u;               // [3][n] per run: physical velocity
+  T* u;               // [3][n] per run: physical velocity (observe / export)
   uint32_t* status;   // per run: bit 0 non-finite, bit 1 tr C >= L^2
 };
 

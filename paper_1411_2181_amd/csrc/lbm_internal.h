@@ -46,17 +46,20 @@ struct AuxArgs {
   const double* rho_init;       // [nruns][2]: rho_major, rho_minor (init only)
 };
 
+// One time step over the tile table: grid.x workgroups (two per tile slot,
+// one per component; see k_step), block (bx, by).
 template <typename T, typename S>
-void launch_force(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s);
-template <typename T, typename S>
-void launch_collide(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s);
-template <typename T, typename S>
-void launch_fene(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s);
+void launch_step(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s);
+// Tile shapes (bx, by) with a compiled instance of the step kernel for the
+// compute type T (the FP64 instance has fewer: its LDS rings are twice as
+// large).
+bool step_shape_ok(int bx, int by, bool fp64);
 
 template <typename T, typename S>
 void launch_init(const AuxArgs<T, S>& a, hipStream_t s);
+// Physical velocity u of every run at its current parity (observe, export).
 template <typename T, typename S>
-void launch_moments(const AuxArgs<T, S>& a, hipStream_t s);
+void launch_flow(const AuxArgs<T, S>& a, hipStream_t s);
 template <typename T, typename S>
 void launch_observe(const AuxArgs<T, S>& a, hipStream_t s);
 template <typename T, typename S>

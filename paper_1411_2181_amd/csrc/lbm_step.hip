@@ -1,324 +1,245 @@
-// Step kernels of the hybrid LB / FENE-P solver (gfx950).
+// Step kernel of the hybrid LB / FENE-P solver (gfx950): one launch per step.
 //
-// One time step n -> n+1 is three launches over the tile table:
+// Dependencies of one step n -> n+1 at a node x:
+//   * the lattice-Boltzmann part pulls the 19 populations that arrive at x,
+//     each collided at its source node s = x - c_i with the equilibrium of s;
+//     that equilibrium needs the force at s: the Shan-Chen force from the
+//     densities of s's neighbours and the polymer force, the centred
+//     divergence of the stress T = chi (eta_P/tau_P)(f C - I) over s's face
+//     neighbours (Section 2, Eqs. (1) and (3));
+//   * the FENE-P update at x (Eqs. (2) and (4)) needs the physical velocity,
+//     hence the force, at x's face neighbours.
+// So a tile of nodes needs the state within two nodes of it: densities and C
+// at radius 2, momenta and populations at radius 1.  The kernel reads exactly
+// that (state n, parity p) and writes state n+1 (parity p^1): populations,
+// densities, momenta and C.  No intermediate field goes through HBM.
 //
-//   force pass    (per node): Shan-Chen force from the densities of the 18
-//                 neighbours (mirror ghost in z), polymer force as the centred
-//                 divergence of T = chi (eta_P/tau_P)(f C - I) over the six
-//                 face neighbours, then the Shan-Chen velocity shift
-//                 u' = sum(j_s/tau_s)/sum(rho_s/tau_s), u^eq_s = u' + tau_s F_s/rho_s
-//                 and the physical velocity u = (j_A + j_B + (F_A+F_B)/2)/rho.
-//                 Writes (rho_s, u^eq_s) per component and u.
-//   collide pass  (per node and component): pull streaming -- each population
-//                 arriving at x is the BGK post-collision value
-//                 f_i - (f_i - f^eq_i)/tau_s of the source node x - c_i,
-//                 computed on the fly from that node's (rho_s, u^eq_s); links
-//                 that cross a wall are replaced by the half-way bounce-back
-//                 of the node's own outgoing population with the moving-wall
-//                 term -6 w_i rho_s c_i.u_wall.  The new density and momentum
-//                 of the component at x are summed from the values written.
-//                 Populations are held as g_i = f_i - w_i rho_s(node) (see
-//                 Store), and the collision is done in that variable.
-//   FENE-P pass   (per node, viscoelastic runs only): explicit Euler step of
-//                 C with u^n and C^n of the six face neighbours (first-order
-//                 upwind advection, centred grad u, Peterlin factor in FP64).
+// Work split.  Two workgroups per tile, one per component s, dispatched to
+// the same XCD (workgroups go round-robin over the 8 XCDs, so ids b and b+8
+// share one): both recompute the forces on the tile and a one-node frame
+// from the same inputs, the second mostly from that XCD's L2.  The workgroup
+// of component s collides and streams s and updates three of the six
+// components of C (xx yy zz for s = A, xy xz yz for s = B).
 //
-// The model is Section 2 of the paper (Eqs. (1)-(4), Peterlin factor below
-// Eq. (2)); the set-up (walls at +-U_w, periodic x and y) is Section 3.
-// Every pass reads the state at parity (base + step) & 1; the collide and
-// FENE-P passes write the other parity, so no node reads a value written in
-// the same pass.  A node's arithmetic does not depend on the tile shape or on
-// the other runs of a batch, so every launch shape and batch composition is
-// bit-identical.
+// z-march.  A workgroup advances its bx*by column block plane by plane.  In
+// the iteration of plane r it
+//   (A) stages plane r of both densities and of the stress T (computed once
+//       per node, Peterlin factor in FP64) on the tile + 2-node frame in LDS,
+//       and C on the 1-node frame;
+//   (D) adds plane r's contributions to the Shan-Chen sums and to the stress
+//       divergence of the 1-frame nodes at planes r-1, r and r+1 (registers:
+//       each thread owns the frame nodes it finalises);
+//   (E) finalises plane r-1: forces, the velocity shift, the records the
+//       collision reads, and the physical velocity, into LDS rings;
+//   (G) collides and streams plane r-2 and updates its C components there.
+// The loads of plane r+1 (densities, C), of the momenta of plane r and of
+// the populations of plane r-1 are in flight while plane r is processed.
+//
+// Storage and collision.  Populations are held as
+// g_i = f_i - w_i (rho + 3 c_i.j) against the moments of the node that holds
+// them (see Store).  With w = 1/tau and the record of the source node s,
+// a = rho (1 - 1.5 w |u^eq|^2), P = w rho u^eq + (1 - w) j (the post-collision
+// momentum), b = 4.5 w rho, the BGK collision f* = (1 - w) f + w f^eq reads
+//   f*_i(s) = (1 - w) g_i(s) + w_i [a + 3 c_i.P + b (c_i.u^eq)^2];
+// the arriving value is re-referenced to the moments of x, the new moments
+// of x are the old ones plus the sums of the re-referenced values, and the
+// value stored is the difference to the new moments.  Every rounding acts on
+// a small difference.
+//
+// The set-up (walls at -+U_w half a link outside z = 0 and z = nz-1, periodic
+// x and y) is Section 3.  A node's arithmetic does not depend on the tile
+// shape or on the other runs of a batch, so every launch shape and batch
+// composition is bit-identical.
 #include "lbm_internal.h"
+
+#include <type_traits>
 
 namespace lbm {
 
-// Equilibrium minus its rest part, f^eq_i - w_i rho (the shifted
-// equilibrium), times a power-of-two storage scale folded into the weight.
-template <typename T>
-__device__ __forceinline__ T geq(int i, T rho, T ux, T uy, T uz, T scale) {
-  const T cu = T(CX[i]) * ux + T(CY[i]) * uy + T(CZ[i]) * uz;
-  const T usq = ux * ux + uy * uy + uz * uz;
-  return (wgt<T>(i) * scale) * rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
-}
+__device__ __forceinline__ int wrapp(int v, int n) { return ((v % n) + n) % n; }
 
-__device__ __forceinline__ int64_t nid(int x, int y, int z, int nx, int ny) {
-  return ((int64_t)z * ny + y) * nx + x;
-}
+// Frame geometry of a BX x BY tile: the 1-node frame (tile + 1 on each side)
+// and the 2-node frame.  Slot 0 of every thread is its own column; the ring
+// positions (frame minus tile) are dealt out over the threads.
+template <int BX, int BY>
+struct Frame {
+  static constexpr int NT = BX * BY;
+  static constexpr int HX1 = BX + 2, HY1 = BY + 2, N1 = HX1 * HY1;
+  static constexpr int HX2 = BX + 4, HY2 = BY + 4, N2 = HX2 * HY2;
+  static constexpr int R1 = N1 - NT, R2 = N2 - NT;
+  static constexpr int K1 = 1 + (R1 + NT - 1) / NT;   // 1-frame positions per thread
+  static constexpr int K2 = 1 + (R2 + NT - 1) / NT;   // 2-frame positions per thread
+  // ring position e < R1 of the 1-frame: bottom row, top row, left, right column
+  static __device__ __forceinline__ void ring1(int e, int& hx, int& hy) {
+    if (e < HX1) { hx = e; hy = 0; }
+    else if (e < 2 * HX1) { hx = e - HX1; hy = HY1 - 1; }
+    else if (e < 2 * HX1 + BY) { hx = 0; hy = e - 2 * HX1 + 1; }
+    else { hx = HX1 - 1; hy = e - 2 * HX1 - BY + 1; }
+  }
+  // ring position e < R2 of the 2-frame: rows 0, 1, HY2-2, HY2-1, then the
+  // columns 0, 1, HX2-2, HX2-1 of rows 2 .. BY+1
+  static __device__ __forceinline__ void ring2(int e, int& hx, int& hy) {
+    if (e < 4 * HX2) {
+      const int row = e / HX2;
+      hx = e - row * HX2;
+      hy = row < 2 ? row : HY2 - 4 + row;
+    } else {
+      const int f = e - 4 * HX2;
+      const int col = f / BY;
+      hy = 2 + (f - col * BY);
+      hx = col < 2 ? col : HX2 - 4 + col;
+    }
+  }
+};
 
-// Optional occupancy target of the collide pass (waves per SIMD), a build
-// option: the register budget then shrinks to 512 / waves.
-#ifdef LBM_COLLIDE_WAVES
-#define LBM_COLLIDE_OCC __attribute__((amdgpu_waves_per_eu(LBM_COLLIDE_WAVES)))
-#else
-#define LBM_COLLIDE_OCC
-#endif
+template <typename T, int BX, int BY>
+struct StepLds {
+  using F = Frame<BX, BY>;
+  T rho[2][F::N2];          // plane r: rho_A, rho_B on the 2-frame
+  T stress[6][F::N2];       // plane r: T on the 2-frame
+  V4<T> rec[3][2][F::N1];   // planes mod 3: (a, P), (u^eq, b) of this component
+  T u[2][3][F::N1];         // planes mod 2: physical velocity
+  T C[3][3][F::N1];         // planes mod 3: this workgroup's three C components
+};
 
-// Planes held in the LDS rings of the force and FENE-P passes.  Three (the
-// minimum for a radius-1 stencil in z) take a second barrier per plane before
-// a slot is overwritten; four need one barrier but 4/3 the LDS, which limits
-// the workgroups per CU.
-#ifndef LBM_RING_SLOTS
-#define LBM_RING_SLOTS 3
-#endif
-constexpr int RS = LBM_RING_SLOTS;
-static_assert(RS == 3 || RS == 4, "ring of 3 or 4 planes");
-// ring slot of plane zp >= -1
-__device__ __forceinline__ int rslot(int zp) { return RS == 4 ? (zp & 3) : (zp + 3) % 3; }
+template <int BX, int BY, typename T>
+constexpr bool step_fits() { return sizeof(StepLds<T, BX, BY>) <= 160 * 1024; }
 
-// Shapes of the tile (bx, by) with a compiled instance of every pass.
-#define LBM_FOR_SHAPES(M) M(64, 4) M(32, 8) M(128, 2) M(64, 2) M(32, 4)
+// Shapes with a compiled instance: FP32 (and FP16 storage) all, FP64 those
+// whose rings fit the 160 KiB of LDS.
+#define LBM_FOR_SHAPES(M) M(32, 8) M(64, 4) M(16, 16) M(32, 16)
 
-// ---- force pass ----------------------------------------------------------------
-// One workgroup marches up the z range of a bx*by tile.  The densities (and,
-// for a viscoelastic run, the polymer stress T computed once per node) of
-// planes z-1, z, z+1 of the tile plus a one-node halo live in an LDS ring;
-// the raw values of plane z+2 are loaded into registers while plane z is
-// computed.  Ghost planes beyond the walls repeat the boundary plane (mirror
-// density, zero-gradient C, hence the same T).
 template <typename T, typename S, int BX, int BY>
-__global__ void __launch_bounds__(BX * BY) k_force(StepArgs<T, S> a) {
-  constexpr int HX = BX + 2, HY = BY + 2, HN = HX * HY, NT = BX * BY;
-  constexpr int KP = (HN + NT - 1) / NT;
-  __shared__ T srho[RS][2][HN];
-  __shared__ T sT[RS][6][HN];
+__global__ void __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(2)))
+k_step(StepArgs<T, S> a) {
+  using F = Frame<BX, BY>;
+  constexpr int NT = F::NT, HX1 = F::HX1, HX2 = F::HX2, K1 = F::K1, K2 = F::K2;
+  static_assert(step_fits<BX, BY, T>(), "LDS rings exceed 160 KiB");
+  __shared__ StepLds<T, BX, BY> L;
+  using St = Store<T, S>;
+  const T kS = T(St::kScale), ikS = T(1.0 / St::kScale);
   const int g = *a.gstep;
   const int tx = (int)threadIdx.x, ty = (int)threadIdx.y, tid = ty * BX + tx;
-  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+  const int b = (int)blockIdx.x;
+  const int s = (b >> 3) & 1;                      // component of this workgroup
+  const int tslot = ((b >> 4) << 3) | (b & 7);     // same tile slot and XCD for s = 0, 1
+  const int tstride = (int)gridDim.x >> 1;
+
+  // frame positions of this thread (independent of the tile)
+  int f1x[K1], f1y[K1], p1[K1], p12[K1];   // 1-frame: coords, LDS index, 2-frame index
+  int f2x[K2], f2y[K2], p2[K2], q1[K2];    // 2-frame: coords, LDS index, 1-frame index (or -1)
+#pragma unroll
+  for (int k = 0; k < K1; ++k) {
+    int hx = tx + 1, hy = ty + 1;
+    if (k > 0) F::ring1(min(tid + (k - 1) * NT, F::R1 - 1), hx, hy);
+    f1x[k] = hx; f1y[k] = hy;
+    p1[k] = hy * HX1 + hx;
+    p12[k] = (hy + 1) * HX2 + hx + 1;
+  }
+#pragma unroll
+  for (int k = 0; k < K2; ++k) {
+    int hx = tx + 2, hy = ty + 2;
+    if (k > 0) F::ring2(min(tid + (k - 1) * NT, F::R2 - 1), hx, hy);
+    f2x[k] = hx; f2y[k] = hy;
+    p2[k] = hy * HX2 + hx;
+    const bool in1 = hx >= 1 && hx <= BX + 2 && hy >= 1 && hy <= BY + 2;
+    q1[k] = in1 ? (hy - 1) * HX1 + (hx - 1) : -1;
+  }
+  const int lc = (ty + 1) * HX1 + (tx + 1);   // own column in the 1-frame
+
+  for (int t = tslot; t < a.ntiles; t += tstride) {
     const Tile tl = a.tiles[t];
     if (tl.run < 0) continue;
     const RunDev& R = a.runs[tl.run];
     if (g >= R.target) continue;
     const int par = (R.base + g) & 1;
-    const int nx = R.nx, ny = R.ny, nz = R.nz;
-    const int x = tl.x0 + tx, y = tl.y0 + ty;
-    const bool active = x < nx && y < ny;
+    const int nx = R.nx, ny = R.ny, nz = R.nz, nxy = nx * ny;
     const bool visc = R.visc >= 0;
     const int64_t N = R.ld;   // stride between the component arrays of a field
-    const T* __restrict__ rho = a.P.rho[par] + 2 * R.off;
-    const T* __restrict__ J = a.P.j[par] + 6 * R.off;
-    const T* __restrict__ C = a.P.C[par] + 6 * R.off;
-    V4<T>* __restrict__ recA = a.P.recA + R.off;
-    V4<T>* __restrict__ recB = a.P.recB + R.off;
-    T* __restrict__ U = a.P.u + 3 * R.off;
+    const int x = tl.x0 + tx, y = tl.y0 + ty;
+    const bool active = x < nx && y < ny;
     // run parameters in registers: a load of them inside the z-march would
-    // wait for every load in flight (the prefetched planes) as well
+    // wait for every load in flight as well
     const T G = T(R.G);
     const T tA = T(R.tau[0]), tB = T(R.tau[1]);
     const T itA = T(R.inv_tau[0]), itB = T(R.inv_tau[1]);
+    const T om = s ? itB : itA;                  // 1/tau of this component
+    const T om1 = T(1) - om;
+    const T uw = T(R.u_wall);
     const int vph = R.visc;
     const T chi_lo = T(R.chi_lo), ichr = T(R.inv_chi_range), eP = T(R.etaP_over_tauP);
+    const T itP = T(R.inv_tauP);
     const double L2 = R.L2;
-    T raw[KP][8];
-    auto load_raw = [&](int zp) {
-      const int zc = zp < 0 ? 0 : (zp >= nz ? nz - 1 : zp);
-#pragma unroll
-      for (int kk = 0; kk < KP; ++kk) {
-        const int k = tid + kk * NT;
-        if (k < HN) {
-          int gx = (tl.x0 + k % HX - 1) % nx;
-          int gy = (tl.y0 + k / HX - 1) % ny;
-          gx += gx < 0 ? nx : 0;
-          gy += gy < 0 ? ny : 0;
-          const int64_t m = nid(gx, gy, zc, nx, ny);
-          raw[kk][0] = rho[m];
-          raw[kk][1] = rho[N + m];
-          if (visc) {
-#pragma unroll
-            for (int c = 0; c < 6; ++c) raw[kk][2 + c] = C[c * N + m];
-          }
-        }
-      }
-    };
-    // T = chi (eta_P/tau_P)(f C - I): chi the clamped rescaled mass fraction
-    // of the polymer phase's component, f the Peterlin factor in FP64
-    auto store_raw = [&](int zp) {
-      const int sl = rslot(zp);
-#pragma unroll
-      for (int kk = 0; kk < KP; ++kk) {
-        const int k = tid + kk * NT;
-        if (k < HN) {
-          const T rA = raw[kk][0], rB = raw[kk][1];
-          srho[sl][0][k] = rA;
-          srho[sl][1][k] = rB;
-          if (visc) {
-            const T rp = vph == 0 ? rA : rB;
-            T chi = (rp / (rA + rB) - chi_lo) * ichr;
-            chi = chi < T(0) ? T(0) : (chi > T(1) ? T(1) : chi);
-            const double tr = (double)raw[kk][2] + (double)raw[kk][3] + (double)raw[kk][4];
-            const T fP = (T)((L2 - 3.0) / (L2 - tr));
-            const T coef = chi * eP;
-#pragma unroll
-            for (int c = 0; c < 6; ++c)
-              sT[sl][c][k] = coef * (fP * raw[kk][2 + c] - (c < 3 ? T(1) : T(0)));
-          }
-        }
-      }
-    };
-    __syncthreads();   // the previous tile's readers are done with the ring
-    const int zend = min(tl.z0 + a.bz, nz);
-    load_raw(tl.z0 - 1);
-    store_raw(tl.z0 - 1);
-    load_raw(tl.z0);
-    store_raw(tl.z0);
-    load_raw(tl.z0 + 1);
-    const int lc = (ty + 1) * HX + (tx + 1);
-    // momenta of the thread's node, one plane ahead (inactive threads of a
-    // ragged tile read a valid node and discard it); the two register sets
-    // alternate roles (the march is unrolled by two planes), so no copy
-    // waits for loads in flight
-    auto load_j = [&](int zz, T (&v)[6]) {
-      const int64_t m = nid(active ? x : 0, active ? y : 0, zz, nx, ny);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) v[c] = J[c * N + m];
-    };
-    auto plane = [&](int z, const T (&jc)[6], T (&jn)[6]) {
-      if (RS == 3) __syncthreads();   // plane z-2's slot is free (plane z-1 done)
-      store_raw(z + 1);
-      // the loads of plane z+2 and of the momenta of plane z+1 stay in
-      // flight while plane z is computed; past the tile's end they re-read
-      // its last planes (in bounds, unused)
-      load_raw(min(z + 2, zend));
-      load_j(min(z + 1, zend - 1), jn);
-      const int64_t n = nid(active ? x : 0, active ? y : 0, z, nx, ny);
-      __syncthreads();
-      if (!active) return;
-      const T jA0 = jc[0], jA1 = jc[1], jA2 = jc[2], jB0 = jc[3], jB1 = jc[4], jB2 = jc[5];
-      // Shan-Chen: F_A = -G rho_A sum_i 3 w_i rho_B(x+c_i) c_i (and A<->B)
-      T sA0 = 0, sA1 = 0, sA2 = 0, sB0 = 0, sB1 = 0, sB2 = 0;
-#pragma unroll
-      for (int i = 1; i < Q; ++i) {
-        const int sl = rslot(z + CZ[i]);
-        const int k = lc + CY[i] * HX + CX[i];
-        const T nA = srho[sl][0][k], nB = srho[sl][1][k];
-        const T wt = T(3) * wgt<T>(i);
-        if (CX[i] != 0) { sA0 += (wt * T(CX[i])) * nB; sB0 += (wt * T(CX[i])) * nA; }
-        if (CY[i] != 0) { sA1 += (wt * T(CY[i])) * nB; sB1 += (wt * T(CY[i])) * nA; }
-        if (CZ[i] != 0) { sA2 += (wt * T(CZ[i])) * nB; sB2 += (wt * T(CZ[i])) * nA; }
-      }
-      const int s0 = rslot(z), sp = rslot(z + 1), sm = rslot(z - 1);
-      const T rA = srho[s0][0][lc], rB = srho[s0][1][lc];
-      const T irt = T(1) / (rA + rB);
-      T FA0 = -G * rA * sA0, FA1 = -G * rA * sA1, FA2 = -G * rA * sA2;
-      T FB0 = -G * rB * sB0, FB1 = -G * rB * sB1, FB2 = -G * rB * sB2;
-      if (visc) {
-        // F^P_a = sum_b [T_ab(x+e_b) - T_ab(x-e_b)]/2
-        const T dx0 = T(0.5) * (sT[s0][0][lc + 1] - sT[s0][0][lc - 1]);
-        const T dx1 = T(0.5) * (sT[s0][3][lc + 1] - sT[s0][3][lc - 1]);
-        const T dx2 = T(0.5) * (sT[s0][4][lc + 1] - sT[s0][4][lc - 1]);
-        const T dy0 = T(0.5) * (sT[s0][3][lc + HX] - sT[s0][3][lc - HX]);
-        const T dy1 = T(0.5) * (sT[s0][1][lc + HX] - sT[s0][1][lc - HX]);
-        const T dy2 = T(0.5) * (sT[s0][5][lc + HX] - sT[s0][5][lc - HX]);
-        const T dz0 = T(0.5) * (sT[sp][4][lc] - sT[sm][4][lc]);
-        const T dz1 = T(0.5) * (sT[sp][5][lc] - sT[sm][5][lc]);
-        const T dz2 = T(0.5) * (sT[sp][2][lc] - sT[sm][2][lc]);
-        T P0 = 0, P1 = 0, P2 = 0;
-        P0 = ((P0 + dx0) + dy0) + dz0;
-        P1 = ((P1 + dx1) + dy1) + dz1;
-        P2 = ((P2 + dx2) + dy2) + dz2;
-        const T fa = rA * irt, fb = rB * irt;
-        FA0 = FA0 + fa * P0; FA1 = FA1 + fa * P1; FA2 = FA2 + fa * P2;
-        FB0 = FB0 + fb * P0; FB1 = FB1 + fb * P1; FB2 = FB2 + fb * P2;
-      }
-      // one reciprocal per denominator
-      const T iden = T(1) / (rA * itA + rB * itB);
-      const T up0 = (jA0 * itA + jB0 * itB) * iden;
-      const T up1 = (jA1 * itA + jB1 * itB) * iden;
-      const T up2 = (jA2 * itA + jB2 * itB) * iden;
-      const T sA = tA / rA, sB = tB / rB;
-      V4<T> ra, rb;
-      ra.x = rA; ra.y = up0 + sA * FA0; ra.z = up1 + sA * FA1; ra.w = up2 + sA * FA2;
-      rb.x = rB; rb.y = up0 + sB * FB0; rb.z = up1 + sB * FB1; rb.w = up2 + sB * FB2;
-      recA[n] = ra;
-      recB[n] = rb;
-      U[n] = (jA0 + jB0 + T(0.5) * (FA0 + FB0)) * irt;
-      U[N + n] = (jA1 + jB1 + T(0.5) * (FA1 + FB1)) * irt;
-      U[2 * N + n] = (jA2 + jB2 + T(0.5) * (FA2 + FB2)) * irt;
-    };
-    T ja[6], jb[6];
-    load_j(tl.z0, ja);
-    for (int z = tl.z0; z < zend; z += 2) {
-      plane(z, ja, jb);
-      if (z + 1 < zend) plane(z + 1, jb, ja);
-    }
-  }
-}
+    const uint32_t hstep = ((uint32_t)(R.base + g) * 2u + (uint32_t)s) * 0x85ebca77u;
 
-// ---- collide + stream pass ------------------------------------------------------
-// One workgroup advances one component (blockIdx.y) of a bx*by tile while it
-// marches up the tile's z range.  The (rho_s, u^eq_s) records of planes z-1,
-// z, z+1 of the tile plus a one-node halo are staged in LDS (a four-slot
-// ring, one barrier per plane): each record is read from HBM about once
-// instead of once by each of its 19 pulling neighbours.
-template <typename T, typename S, int BX, int BY>
-__global__ void __launch_bounds__(BX * BY) LBM_COLLIDE_OCC k_collide(StepArgs<T, S> a) {
-  constexpr int HX = BX + 2, HY = BY + 2, HN = HX * HY, NT = BX * BY;
-  constexpr int KR = (HN + NT - 1) / NT;   // records staged per thread and plane
-  __shared__ V4<T> ring[4][HN];
-  const int g = *a.gstep;
-  const int s = (int)blockIdx.y;
-  const int tx = (int)threadIdx.x, ty = (int)threadIdx.y, tid = ty * BX + tx;
-  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-    const Tile tl = a.tiles[t];
-    if (tl.run < 0) continue;
-    const RunDev& R = a.runs[tl.run];
-    if (g >= R.target) continue;
-    const int par = (R.base + g) & 1;
-    const int nx = R.nx, ny = R.ny, nz = R.nz;
-    const int x = tl.x0 + tx, y = tl.y0 + ty;
-    const bool active = x < nx && y < ny;
-    const int64_t N = R.ld;   // stride between the component arrays of a field
+    const T* __restrict__ rho_in = a.P.rho[par] + 2 * R.off;
+    const T* __restrict__ J_in = a.P.j[par] + 6 * R.off;
+    const T* __restrict__ C_in = a.P.C[par] + 6 * R.off;
     const S* __restrict__ fs = a.P.f[par] + (38 * R.off + (int64_t)s * Q * N);
     S* __restrict__ fo = a.P.f[par ^ 1] + (38 * R.off + (int64_t)s * Q * N);
     T* __restrict__ rho_out = a.P.rho[par ^ 1] + 2 * R.off + s * N;
     T* __restrict__ j_out = a.P.j[par ^ 1] + 6 * R.off + 3 * s * N;
-    const V4<T>* __restrict__ rec = (s == 0 ? a.P.recA : a.P.recB) + R.off;
-    // inactive threads of a ragged tile address the edge node (their loads
-    // are in bounds and their values unused)
+    T* __restrict__ C_out = a.P.C[par ^ 1] + 6 * R.off;
+
+    // plane offsets of the frame positions (periodic in x and y)
+    int col1[K1], col2[K2];
+#pragma unroll
+    for (int k = 0; k < K1; ++k)
+      col1[k] = wrapp(tl.y0 + f1y[k] - 1, ny) * nx + wrapp(tl.x0 + f1x[k] - 1, nx);
+#pragma unroll
+    for (int k = 0; k < K2; ++k)
+      col2[k] = wrapp(tl.y0 + f2y[k] - 2, ny) * nx + wrapp(tl.x0 + f2x[k] - 2, nx);
+
+    // Pulls: byte offsets inside one direction array (a run's array is
+    // < 4 GiB, which the library checks).  Inactive threads of a ragged tile
+    // address the edge node (loads in bounds, values unused).
     const int xq = x < nx ? x : nx - 1, yq = y < ny ? y : ny - 1;
     const int xm = xq == 0 ? nx - 1 : xq - 1, xp = xq >= nx - 1 ? 0 : xq + 1;
     const int ym = yq == 0 ? ny - 1 : yq - 1, yp = yq >= ny - 1 ? 0 : yq + 1;
-    // run parameters in registers: a load of them inside the z-march would
-    // wait for the populations in flight as well
-    const T uw = T(R.u_wall);
-    const T it = T(R.inv_tau[s]);
-    const uint32_t hstep = ((uint32_t)(R.base + g) * 2u + (uint32_t)s) * 0x85ebca77u;
-    using St = Store<T, S>;
-    const T kS = T(St::kScale), ikS = T(1.0 / St::kScale);
-    // records of plane zp of the tile + halo (periodic in x and y), the
-    // kk-th of each thread: loaded into registers ahead of the populations,
-    // so that writing them to the ring waits for these loads only.  Threads
-    // past the halo's end load and rewrite its last record (no branch, so
-    // the loads stay where they are issued).
-    static_assert(KR <= 3, "at most three records per thread and plane");
-    auto rec_at = [&](int zp, int kk) -> V4<T> {
-      const int k = min(tid + kk * NT, HN - 1);
-      int gx = (tl.x0 + k % HX - 1) % nx;
-      int gy = (tl.y0 + k / HX - 1) % ny;
-      gx += gx < 0 ? nx : 0;
-      gy += gy < 0 ? ny : 0;
-      return rec[nid(gx, gy, zp, nx, ny)];
-    };
-    auto rec_put = [&](int zp, int kk, const V4<T>& v) {
-      ring[zp & 3][min(tid + kk * NT, HN - 1)] = v;
-    };
-    // Byte offsets inside one direction array (a run's array is < 4 GiB, which
-    // the library checks): the plane term is uniform, rows and columns
-    // (periodic) are per thread, and the array base is uniform, so every
-    // population access is a uniform base plus one 32-bit offset.
     constexpr uint32_t SB = sizeof(S);
-    const uint32_t pb = (uint32_t)nx * (uint32_t)ny * SB;
+    const uint32_t pb = (uint32_t)nxy * SB;
     const uint32_t rowb[3] = {(uint32_t)(ym * nx) * SB, (uint32_t)(yq * nx) * SB,
                               (uint32_t)(yp * nx) * SB};
     const uint32_t colb[3] = {(uint32_t)xm * SB, (uint32_t)xq * SB, (uint32_t)xp * SB};
     auto arr = [&](const S* base, int i, uint32_t off) {
       return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base + (int64_t)i * N) + off);
     };
-    // the populations that arrive at (x, y, zz): pulled from x - c_i, or the
-    // node's own opposite population where the link crosses a wall
-    auto load_plane = [&](int zz, T (&v)[Q]) {
-      const uint32_t own = (uint32_t)zz * pb + rowb[1] + colb[1];
+    const int own = yq * nx + xq;
+
+    struct Buf {
+      T f[Q];        // populations arriving at the own column (one plane)
+      T j[K1][6];    // momenta of the 1-frame positions (one plane)
+    };
+    T raw[K2][8];    // densities and C of the 2-frame positions (next plane)
+
+    // ---- loads ---------------------------------------------------------------
+    auto load_raw = [&](int r) {
+      const int zo = clampz(r, nz) * nxy;
+#pragma unroll
+      for (int k = 0; k < K2; ++k) {
+        const int m = zo + col2[k];
+        raw[k][0] = rho_in[m];
+        raw[k][1] = rho_in[N + m];
+        if (visc) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) raw[k][2 + c] = C_in[c * N + m];
+        }
+      }
+    };
+    auto load_j = [&](int r, T (&jv)[K1][6]) {
+      const int zo = clampz(r, nz) * nxy;
+#pragma unroll
+      for (int k = 0; k < K1; ++k) {
+        const int m = zo + col1[k];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) jv[k][c] = J_in[c * N + m];
+      }
+    };
+    // populations arriving at the own column in plane zz: pulled from
+    // x - c_i, or the node's own opposite population where the link crosses
+    // a wall (the choice is uniform and made by selects)
+    auto load_pops = [&](int zz, T (&v)[Q]) {
+      const uint32_t ownb = (uint32_t)zz * pb + rowb[1] + colb[1];
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         const int zs = zz - CZ[i];
@@ -326,221 +247,279 @@ __global__ void __launch_bounds__(BX * BY) LBM_COLLIDE_OCC k_collide(StepArgs<T,
         if (CZ[i] == 0) {
           v[i] = St::load(arr(fs, i, off), 0);
         } else {
-          // uniform choice between the pulled value and the wall's reflection
-          // of the node's own opposite population, made by selects so that
-          // the plane's loads issue back to back
           const bool in = zs >= 0 && zs < nz;
-          v[i] = St::load(arr(fs, in ? i : OPPI[i], in ? off : own), 0);
+          v[i] = St::load(arr(fs, in ? i : OPPI[i], in ? off : ownb), 0);
         }
       }
     };
-    __syncthreads();   // the previous tile's readers are done with the ring
-    const int zend = min(tl.z0 + a.bz, nz);
-    for (int zp = max(tl.z0 - 1, 0); zp <= tl.z0; ++zp)
-      for (int kk = 0; kk < KR; ++kk) rec_put(zp, kk, rec_at(zp, kk));
-    // software pipeline: the populations of plane z+1 are in flight while
-    // plane z is collided; the two register sets alternate roles (the march
-    // is unrolled by two planes), so no copy is made between planes.  The
-    // loads are unconditional (past the tile's end they re-read its last
-    // plane, past the lattice's end its top plane): a load skipped on some
-    // path would make the compiler wait for all of them before plane z.
-    auto plane = [&](int z, T (&cur)[Q], T (&nxt)[Q]) {
-      {
-        const int zr = min(z + 1, nz - 1);
-        const V4<T> r0 = rec_at(zr, 0);
-        const V4<T> r1 = KR > 1 ? rec_at(zr, 1) : r0;
-        const V4<T> r2 = KR > 2 ? rec_at(zr, 2) : r0;
-        __builtin_amdgcn_sched_barrier(0);   // the record loads issue first
-        load_plane(min(z + 1, zend - 1), nxt);
-        if (z + 1 < nz) {
-          rec_put(z + 1, 0, r0);
-          if (KR > 1) rec_put(z + 1, 1, r1);
-          if (KR > 2) rec_put(z + 1, 2, r2);
-        }
-      }
-      __syncthreads();
-      if (active) {
-        const int64_t n = nid(x, y, z, nx, ny);
-        const uint32_t nb = (uint32_t)z * pb + rowb[1] + colb[1];   // n * sizeof(S)
-        const int lc = (ty + 1) * HX + (tx + 1);
-        // BGK collision of each arriving population in the shifted variable
-        // of the node that holds it (the record's node in both branches),
-        // g* = g - (g - g^eq)/tau, then re-referenced to the density rho_x of
-        // x: h_i = g*_i + w_i (rho_src,i - rho_x) = f*_i - w_i rho_x.  The new
-        // density is rho_x + sum_i h_i (sum_i w_i = 1): rho_x enters with
-        // weight exactly 1 and the rounded weights (FP32 sum 1 + 1.5e-8) only
-        // multiply small differences, so they do not leak into the mass.
-        // Shifted values are in storage units (times kScale, a power of 2).
-        const T rx = ring[z & 3][lc].x;
-        T drho = 0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          const int zs = z - CZ[i];
-          if (CZ[i] == 0) {
-            const V4<T> r = ring[z & 3][lc - CY[i] * HX - CX[i]];
-            cur[i] = cur[i] - (cur[i] - geq<T>(i, r.x, r.y, r.z, r.w, kS)) * it;
-            if (i != 0) cur[i] += (wgt<T>(i) * kS) * (r.x - rx);
-          } else {
-            // Links through z: the pulled value, or (where the link crosses a
-            // wall) the half-way bounce-back of x's own population in
-            // o = opp(i), whose equilibrium has c_o = -c_i and which gains
-            // the moving-wall term -6 w rho c_o.u_wall.  The choice is uniform
-            // and made by selects; the re-reference term vanishes for the
-            // bounce-back (its record is x's own).
-            const bool in = zs >= 0 && zs < nz;
-            const int o = OPPI[i];
-            const V4<T> r = ring[in ? (zs & 3) : (z & 3)][in ? lc - CY[i] * HX - CX[i] : lc];
-            const T sg = in ? T(1) : T(-1);
-            const T cu = sg * (T(CX[i]) * r.y + T(CY[i]) * r.z + T(CZ[i]) * r.w);
-            const T usq = r.y * r.y + r.z * r.z + r.w * r.w;
-            const T ge = (wgt<T>(i) * kS) * r.x * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
-            const T uwall = CZ[o] > 0 ? uw : -uw;
-            const T wall = in ? T(0) : ((T(6) * kS * wgt<T>(o)) * r.x) * (T(CX[o]) * uwall);
-            cur[i] = cur[i] - (cur[i] - ge) * it - wall;
-            cur[i] += (wgt<T>(i) * kS) * (r.x - rx);
-          }
-          drho += cur[i];
-        }
-        const T rsum = rx + drho * ikS;
-        // stored: f*_i - w_i rho_x_new = h_i - w_i drho; the momentum is
-        // summed from the values as stored (the rest parts cancel pairwise
-        // in sum_i c_i w_i).  FP16 rounding takes 13 random bits per value:
-        // a hash of (node, component, step) starts a Weyl sequence over the
-        // directions (uniform for every direction, independent of the tile
-        // shape and batch layout, and reproducible).
-        uint32_t hb = 0;
-        if (St::kRandom) hb = fmix32((uint32_t)n * 0x9e3779b1u ^ hstep);
-        T jx = 0, jy = 0, jz = 0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          const uint32_t rb = (hb + (uint32_t)i * 0x9e3779b9u) >> 19;
-          const T v = cur[i] - wgt<T>(i) * drho;
-          S* dst = reinterpret_cast<S*>(reinterpret_cast<char*>(fo + (int64_t)i * N) + nb);
-          const T fq = St::put(dst, 0, v, rb);
-          if (CX[i] != 0) jx += T(CX[i]) * fq;
-          if (CY[i] != 0) jy += T(CY[i]) * fq;
-          if (CZ[i] != 0) jz += T(CZ[i]) * fq;
-        }
-        jx *= ikS;
-        jy *= ikS;
-        jz *= ikS;
-        rho_out[n] = rsum;
-        j_out[n] = jx;
-        j_out[N + n] = jy;
-        j_out[2 * N + n] = jz;
-        if (!isfinite(rsum + jx + jy + jz)) atomicOr(a.P.status + tl.run, ST_NAN);
-      }
-    };
-    T va[Q], vb[Q];
-    load_plane(tl.z0, va);
-    for (int z = tl.z0; z < zend; z += 2) {
-      plane(z, va, vb);
-      if (z + 1 < zend) plane(z + 1, vb, va);
-    }
-  }
-}
 
-// ---- FENE-P pass -------------------------------------------------------------------
-// Same z-march as the force pass: C and u of planes z-1, z, z+1 (+ halo) in an
-// LDS ring, plane z+2 loaded into registers while plane z is updated.  Ghost
-// planes: C zero-gradient; u extrapolated through the wall velocity,
-// u(-1) = 2 u_bot - u(0), u(nz) = 2 u_top - u(nz-1), u_wall = (-+U_w, 0, 0).
-template <typename T, typename S, int BX, int BY>
-__global__ void __launch_bounds__(BX * BY) k_fene(StepArgs<T, S> a) {
-  constexpr int HX = BX + 2, HY = BY + 2, HN = HX * HY, NT = BX * BY;
-  constexpr int KP = (HN + NT - 1) / NT;
-  __shared__ T sC[RS][6][HN];
-  __shared__ T sU[RS][3][HN];
-  const int g = *a.gstep;
-  const int tx = (int)threadIdx.x, ty = (int)threadIdx.y, tid = ty * BX + tx;
-  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-    const Tile tl = a.tiles[t];
-    if (tl.run < 0) continue;
-    const RunDev& R = a.runs[tl.run];
-    if (g >= R.target || R.visc < 0) continue;
-    const int par = (R.base + g) & 1;
-    const int nx = R.nx, ny = R.ny, nz = R.nz;
-    const int x = tl.x0 + tx, y = tl.y0 + ty;
-    const bool active = x < nx && y < ny;
-    const int64_t N = R.ld;   // stride between the component arrays of a field
-    const T* __restrict__ Cin = a.P.C[par] + 6 * R.off;
-    T* __restrict__ Cout = a.P.C[par ^ 1] + 6 * R.off;
-    const T* __restrict__ U = a.P.u + 3 * R.off;
-    const T uw = T(R.u_wall);
-    const T itP = T(R.inv_tauP);
-    T raw[KP][9];
-    auto load_raw = [&](int zp) {
-      const int zc = zp < 0 ? 0 : (zp >= nz ? nz - 1 : zp);
+    // ---- per-thread pipeline state ----------------------------------------------
+    T acc[3][K1][9];     // planes r-1, r, r+1: Shan-Chen sums for A, for B; stress divergence
+    T rsv[2][K1][2];     // densities of the 1-frame positions: [0] plane r-1, [1] plane r
+    T Cown[4][6];        // own column C: planes r, r-1, r-2, r-3
+    T rown[3];           // own column density of this component: planes r, r-1, r-2
+    T uown[3][3];        // own column velocity: planes q-1, q, q+1 (q = r-2)
+    T jown[2][3];        // own column momentum of this component: planes r-2, r-1
 #pragma unroll
-      for (int kk = 0; kk < KP; ++kk) {
-        const int k = tid + kk * NT;
-        if (k < HN) {
-          int gx = (tl.x0 + k % HX - 1) % nx;
-          int gy = (tl.y0 + k / HX - 1) % ny;
-          gx += gx < 0 ? nx : 0;
-          gy += gy < 0 ? ny : 0;
-          const int64_t m = nid(gx, gy, zc, nx, ny);
+    for (int p = 0; p < 3; ++p)
 #pragma unroll
-          for (int c = 0; c < 6; ++c) raw[kk][c] = Cin[c * N + m];
+      for (int k = 0; k < K1; ++k)
 #pragma unroll
-          for (int b = 0; b < 3; ++b) raw[kk][6 + b] = U[b * N + m];
-        }
-      }
-    };
-    auto store_raw = [&](int zp) {
-      const int sl = rslot(zp);
+        for (int c = 0; c < 9; ++c) acc[p][k][c] = T(0);
+    uint32_t st = 0;
+
+    // (A) stage plane r
+    auto ingest = [&](int r) {
+      const int sl3 = (r + 3) % 3;
 #pragma unroll
-      for (int kk = 0; kk < KP; ++kk) {
-        const int k = tid + kk * NT;
-        if (k < HN) {
+      for (int k = 0; k < K2; ++k) {
+        const T rA = raw[k][0], rB = raw[k][1];
+        L.rho[0][p2[k]] = rA;
+        L.rho[1][p2[k]] = rB;
+        if (visc) {
+          // T = chi (eta_P/tau_P)(f C - I): chi the clamped rescaled mass
+          // fraction of the polymer phase's component, f in FP64
+          const T rp = vph == 0 ? rA : rB;
+          T chi = (rp / (rA + rB) - chi_lo) * ichr;
+          chi = chi < T(0) ? T(0) : (chi > T(1) ? T(1) : chi);
+          const double tr = (double)raw[k][2] + (double)raw[k][3] + (double)raw[k][4];
+          const T fP = (T)((L2 - 3.0) / (L2 - tr));
+          const T coef = chi * eP;
 #pragma unroll
-          for (int c = 0; c < 6; ++c) sC[sl][c][k] = raw[kk][c];
-          if (zp < 0) {
-            sU[sl][0][k] = T(2) * (-uw) - raw[kk][6];
-            sU[sl][1][k] = T(2) * T(0) - raw[kk][7];
-            sU[sl][2][k] = T(2) * T(0) - raw[kk][8];
-          } else if (zp >= nz) {
-            sU[sl][0][k] = T(2) * uw - raw[kk][6];
-            sU[sl][1][k] = T(2) * T(0) - raw[kk][7];
-            sU[sl][2][k] = T(2) * T(0) - raw[kk][8];
-          } else {
+          for (int c = 0; c < 6; ++c)
+            L.stress[c][p2[k]] = coef * (fP * raw[k][2 + c] - (c < 3 ? T(1) : T(0)));
+          if (q1[k] >= 0) {
 #pragma unroll
-            for (int b = 0; b < 3; ++b) sU[sl][b][k] = raw[kk][6 + b];
+            for (int kk = 0; kk < 3; ++kk) L.C[sl3][kk][q1[k]] = s ? raw[k][5 + kk] : raw[k][2 + kk];
           }
         }
       }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        Cown[3][c] = Cown[2][c];
+        Cown[2][c] = Cown[1][c];
+        Cown[1][c] = Cown[0][c];
+        Cown[0][c] = raw[0][2 + c];
+      }
+      rown[2] = rown[1];
+      rown[1] = rown[0];
+      rown[0] = s ? raw[0][1] : raw[0][0];
     };
-    __syncthreads();   // the previous tile's readers are done with the ring
-    const int zend = min(tl.z0 + a.bz, nz);
-    load_raw(tl.z0 - 1);
-    store_raw(tl.z0 - 1);
-    load_raw(tl.z0);
-    store_raw(tl.z0);
-    load_raw(tl.z0 + 1);
-    const int lc = (ty + 1) * HX + (tx + 1);
-    uint32_t st = 0;
-    for (int z = tl.z0; z < zend; ++z) {
-      if (RS == 3) __syncthreads();   // plane z-2's slot is free (plane z-1 done)
-      store_raw(z + 1);
-      if (z + 2 <= zend) load_raw(z + 2);
-      __syncthreads();
-      if (!active) continue;
-      const int64_t n = nid(x, y, z, nx, ny);
-      const int s0 = rslot(z), sp = rslot(z + 1), sm = rslot(z - 1);
-      const T u0 = sU[s0][0][lc], u1 = sU[s0][1][lc], u2 = sU[s0][2][lc];
+
+    // (D) contributions of plane r to the sums of the 1-frame nodes
+    auto accumulate = [&]() {
+#pragma unroll
+      for (int k = 0; k < K1; ++k) {
+        const int c2 = p12[k];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+          // the node at plane r - c_z reaches plane r through link i
+          const int pl = 1 - CZ[i];
+          const int nb = c2 + CY[i] * HX2 + CX[i];
+          const T nA = L.rho[0][nb], nB = L.rho[1][nb];
+          const T wt = T(3) * wgt<T>(i);
+          if (CX[i] != 0) { acc[pl][k][0] += (wt * T(CX[i])) * nB; acc[pl][k][3] += (wt * T(CX[i])) * nA; }
+          if (CY[i] != 0) { acc[pl][k][1] += (wt * T(CY[i])) * nB; acc[pl][k][4] += (wt * T(CY[i])) * nA; }
+          if (CZ[i] != 0) { acc[pl][k][2] += (wt * T(CZ[i])) * nB; acc[pl][k][5] += (wt * T(CZ[i])) * nA; }
+        }
+        if (visc) {
+          // F^P_a = sum_b [T_ab(x+e_b) - T_ab(x-e_b)]/2: the x and y terms
+          // from plane r; T_az(r) enters the node above with + and the node
+          // below with -
+          const T dx0 = T(0.5) * (L.stress[0][c2 + 1] - L.stress[0][c2 - 1]);
+          const T dx1 = T(0.5) * (L.stress[3][c2 + 1] - L.stress[3][c2 - 1]);
+          const T dx2 = T(0.5) * (L.stress[4][c2 + 1] - L.stress[4][c2 - 1]);
+          const T dy0 = T(0.5) * (L.stress[3][c2 + HX2] - L.stress[3][c2 - HX2]);
+          const T dy1 = T(0.5) * (L.stress[1][c2 + HX2] - L.stress[1][c2 - HX2]);
+          const T dy2 = T(0.5) * (L.stress[5][c2 + HX2] - L.stress[5][c2 - HX2]);
+          acc[1][k][6] += dx0 + dy0;
+          acc[1][k][7] += dx1 + dy1;
+          acc[1][k][8] += dx2 + dy2;
+          const T z0h = T(0.5) * L.stress[4][c2], z1h = T(0.5) * L.stress[5][c2];
+          const T z2h = T(0.5) * L.stress[2][c2];
+          acc[0][k][6] += z0h; acc[0][k][7] += z1h; acc[0][k][8] += z2h;
+          acc[2][k][6] -= z0h; acc[2][k][7] -= z1h; acc[2][k][8] -= z2h;
+        }
+        rsv[1][k][0] = L.rho[0][c2];
+        rsv[1][k][1] = L.rho[1][c2];
+      }
+    };
+
+    // (E) plane m = r-1 of the 1-frame: forces, velocity shift, records, u
+    auto finalise = [&](int m, bool want, const T (&jv)[K1][6]) {
+      const int sl3 = (m + 3) % 3, sl2 = m & 1;
+      T un[3] = {T(0), T(0), T(0)}, jn[3] = {T(0), T(0), T(0)};
+      if (want) {
+#pragma unroll
+        for (int k = 0; k < K1; ++k) {
+          const T rA = rsv[0][k][0], rB = rsv[0][k][1];
+          // Shan-Chen: F_A = -G rho_A sum_i 3 w_i rho_B(x+c_i) c_i (and A<->B)
+          T FA[3], FB[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            FA[c] = -G * rA * acc[0][k][c];
+            FB[c] = -G * rB * acc[0][k][3 + c];
+          }
+          const T irt = T(1) / (rA + rB);
+          if (visc) {
+            // polymer force split over the components by mass fraction
+            const T fa = rA * irt, fb = rB * irt;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              FA[c] = FA[c] + fa * acc[0][k][6 + c];
+              FB[c] = FB[c] + fb * acc[0][k][6 + c];
+            }
+          }
+          // velocity shift u' = sum(j_s/tau_s)/sum(rho_s/tau_s),
+          // u^eq_s = u' + tau_s F_s/rho_s
+          const T iden = T(1) / (rA * itA + rB * itB);
+          const T sA = tA / rA, sB = tB / rB;
+          T ue[3], js[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const T up = (jv[k][c] * itA + jv[k][3 + c] * itB) * iden;
+            ue[c] = s ? up + sB * FB[c] : up + sA * FA[c];
+            js[c] = s ? jv[k][3 + c] : jv[k][c];
+          }
+          const T rs = s ? rB : rA;
+          const T wr = om * rs;
+          const T usq = ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2];
+          V4<T> r0, r1;
+          r0.x = rs - T(1.5) * wr * usq;
+          r0.y = wr * ue[0] + om1 * js[0];
+          r0.z = wr * ue[1] + om1 * js[1];
+          r0.w = wr * ue[2] + om1 * js[2];
+          r1.x = ue[0]; r1.y = ue[1]; r1.z = ue[2];
+          r1.w = T(4.5) * wr;
+          L.rec[sl3][0][p1[k]] = r0;
+          L.rec[sl3][1][p1[k]] = r1;
+          if (visc) {
+            // physical velocity u = (j_A + j_B + (F_A + F_B)/2)/rho
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const T uc = (jv[k][c] + jv[k][3 + c] + T(0.5) * (FA[c] + FB[c])) * irt;
+              L.u[sl2][c][p1[k]] = uc;
+              if (k == 0) un[c] = uc;
+            }
+          }
+          if (k == 0) { jn[0] = js[0]; jn[1] = js[1]; jn[2] = js[2]; }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        uown[0][c] = uown[1][c];
+        uown[1][c] = uown[2][c];
+        uown[2][c] = un[c];
+        jown[0][c] = jown[1][c];
+        jown[1][c] = jn[c];
+      }
+#pragma unroll
+      for (int k = 0; k < K1; ++k) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          acc[0][k][c] = acc[1][k][c];
+          acc[1][k][c] = acc[2][k][c];
+          acc[2][k][c] = T(0);
+        }
+        rsv[0][k][0] = rsv[1][k][0];
+        rsv[0][k][1] = rsv[1][k][1];
+      }
+    };
+
+    // (G) collide and stream this component into plane q of the own column
+    auto collide = [&](int q, T (&v)[Q]) {
+      const int n = q * nxy + own;
+      const uint32_t nb = (uint32_t)n * SB;
+      const int slq = (q + 3) % 3, slm = (q + 2) % 3, slp = (q + 4) % 3;
+      const T rx = rown[2];
+      const T jx0 = jown[0][0], jx1 = jown[0][1], jx2 = jown[0][2];
+      T drho = 0, dj0 = 0, dj1 = 0, dj2 = 0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        int sl = slq, src = lc - CY[i] * HX1 - CX[i];
+        T sg = T(1), wall = T(0);
+        if (CZ[i] != 0) {
+          // links through z: the pulled value, or (where the link crosses a
+          // wall) the half-way bounce-back of x's own population in
+          // o = opp(i), with c_o = -c_i and the moving-wall term
+          // -6 w_o rho c_o.u_wall
+          const int zs = q - CZ[i];
+          const bool in = zs >= 0 && zs < nz;
+          const int o = OPPI[i];
+          sl = in ? (CZ[i] > 0 ? slm : slp) : slq;
+          src = in ? src : lc;
+          sg = in ? T(1) : T(-1);
+          const T uwall = CZ[o] > 0 ? uw : -uw;
+          wall = in ? T(0) : ((T(6) * kS * wgt<T>(o)) * rx) * (T(CX[o]) * uwall);
+        }
+        const V4<T> r0 = L.rec[sl][0][src], r1 = L.rec[sl][1][src];
+        T cP = 0, cu = 0, cj = 0;
+        if (CX[i] != 0) { cP += T(CX[i]) * r0.y; cu += T(CX[i]) * r1.x; cj += T(CX[i]) * jx0; }
+        if (CY[i] != 0) { cP += T(CY[i]) * r0.z; cu += T(CY[i]) * r1.y; cj += T(CY[i]) * jx1; }
+        if (CZ[i] != 0) { cP += T(CZ[i]) * r0.w; cu += T(CZ[i]) * r1.z; cj += T(CZ[i]) * jx2; }
+        cP *= sg;
+        cu *= sg;
+        const T e = (r0.x - rx) + T(3) * (cP - cj) + r1.w * cu * cu;
+        const T h = om1 * v[i] + (wgt<T>(i) * kS) * e - wall;
+        v[i] = h;
+        drho += h;
+        if (CX[i] != 0) dj0 += T(CX[i]) * h;
+        if (CY[i] != 0) dj1 += T(CY[i]) * h;
+        if (CZ[i] != 0) dj2 += T(CZ[i]) * h;
+      }
+      // new moments; stored values against them.  FP16 rounding takes a
+      // random word per value: a hash of (node, component, step) starts a
+      // Weyl sequence over the directions (independent of the tile shape and
+      // batch layout, and reproducible).
+      const T rnew = rx + drho * ikS;
+      const T jn0 = jx0 + dj0 * ikS, jn1 = jx1 + dj1 * ikS, jn2 = jx2 + dj2 * ikS;
+      uint32_t hb = 0;
+      if (St::kRandom) hb = fmix32((uint32_t)n * 0x9e3779b1u ^ hstep);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        T cd = 0;
+        if (CX[i] != 0) cd += T(CX[i]) * dj0;
+        if (CY[i] != 0) cd += T(CY[i]) * dj1;
+        if (CZ[i] != 0) cd += T(CZ[i]) * dj2;
+        const T out = v[i] - wgt<T>(i) * (drho + T(3) * cd);
+        S* dst = reinterpret_cast<S*>(reinterpret_cast<char*>(fo + (int64_t)i * N) + nb);
+        St::put(dst, 0, out, hb + (uint32_t)i * 0x9e3779b9u);
+      }
+      rho_out[n] = rnew;
+      j_out[n] = jn0;
+      j_out[N + n] = jn1;
+      j_out[2 * N + n] = jn2;
+      if (!isfinite(rnew + jn0 + jn1 + jn2)) st |= ST_NAN;
+    };
+
+    // (G) FENE-P for this workgroup's C components at plane q of the own
+    // column: C^{n+1} = C - A + S - (f C - I)/tau_P with centred grad u,
+    // first-order upwind A and S_kl = sum_m C_km G_ml + G_mk C_ml.  Ghost
+    // planes: C zero-gradient (the clamped planes), u extrapolated through
+    // the wall velocity, u(-1) = 2 u_bot - u(0), u(nz) = 2 u_top - u(nz-1).
+    auto fene = [&](int q, auto half) {
+      constexpr int base = decltype(half)::value * 3;
+      const int n = q * nxy + own;
+      const int slu = q & 1, slc = (q + 3) % 3;
+      const T u0 = uown[1][0], u1 = uown[1][1], u2 = uown[1][2];
+      T um[3], up[3];
+      if (q == 0) { um[0] = T(2) * (-uw) - u0; um[1] = -u1; um[2] = -u2; }
+      else { um[0] = uown[0][0]; um[1] = uown[0][1]; um[2] = uown[0][2]; }
+      if (q == nz - 1) { up[0] = T(2) * uw - u0; up[1] = -u1; up[2] = -u2; }
+      else { up[0] = uown[2][0]; up[1] = uown[2][1]; up[2] = uown[2][2]; }
       T Gm[3][3];
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        Gm[0][b] = T(0.5) * (sU[s0][b][lc + 1] - sU[s0][b][lc - 1]);
-        Gm[1][b] = T(0.5) * (sU[s0][b][lc + HX] - sU[s0][b][lc - HX]);
-        Gm[2][b] = T(0.5) * (sU[sp][b][lc] - sU[sm][b][lc]);
+      for (int bb = 0; bb < 3; ++bb) {
+        Gm[0][bb] = T(0.5) * (L.u[slu][bb][lc + 1] - L.u[slu][bb][lc - 1]);
+        Gm[1][bb] = T(0.5) * (L.u[slu][bb][lc + HX1] - L.u[slu][bb][lc - HX1]);
+        Gm[2][bb] = T(0.5) * (up[bb] - um[bb]);
       }
       T c[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) c[k] = sC[s0][k][lc];
+      for (int i = 0; i < 6; ++i) c[i] = Cown[2][i];
       const double tr = (double)c[0] + (double)c[1] + (double)c[2];
-      if (tr >= R.L2) st |= ST_FENE;
-      const T fP = (T)((R.L2 - 3.0) / (R.L2 - tr));
+      if (base == 0 && tr >= L2) st |= ST_FENE;
+      const T fP = (T)((L2 - 3.0) / (L2 - tr));
       const T ua0 = u0 > T(0) ? u0 : T(0), ub0 = u0 < T(0) ? u0 : T(0);
       const T ua1 = u1 > T(0) ? u1 : T(0), ub1 = u1 < T(0) ? u1 : T(0);
       const T ua2 = u2 > T(0) ? u2 : T(0), ub2 = u2 < T(0) ? u2 : T(0);
@@ -549,61 +528,166 @@ __global__ void __launch_bounds__(BX * BY) k_fene(StepArgs<T, S> a) {
       constexpr int SYM[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
       T csum = 0;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
+      for (int kk = 0; kk < 3; ++kk) {
+        const int k = base + kk;
         const T ck = c[k];
         T adv = 0;
-        adv += ua0 * (ck - sC[s0][k][lc - 1]) + ub0 * (sC[s0][k][lc + 1] - ck);
-        adv += ua1 * (ck - sC[s0][k][lc - HX]) + ub1 * (sC[s0][k][lc + HX] - ck);
-        adv += ua2 * (ck - sC[sm][k][lc]) + ub2 * (sC[sp][k][lc] - ck);
+        adv += ua0 * (ck - L.C[slc][kk][lc - 1]) + ub0 * (L.C[slc][kk][lc + 1] - ck);
+        adv += ua1 * (ck - L.C[slc][kk][lc - HX1]) + ub1 * (L.C[slc][kk][lc + HX1] - ck);
+        adv += ua2 * (ck - Cown[3][k]) + ub2 * (Cown[1][k] - ck);
         T Sk = 0;
 #pragma unroll
-        for (int m = 0; m < 3; ++m)
-          Sk += c[SYM[KK[k]][m]] * Gm[m][LL[k]] + Gm[m][KK[k]] * c[SYM[m][LL[k]]];
+        for (int mm = 0; mm < 3; ++mm)
+          Sk += c[SYM[KK[k]][mm]] * Gm[mm][LL[k]] + Gm[mm][KK[k]] * c[SYM[mm][LL[k]]];
         const T delta = k < 3 ? T(1) : T(0);
         const T cn = ck + (-adv + Sk - (fP * ck - delta) * itP);
-        Cout[k * N + n] = cn;
+        C_out[k * N + n] = cn;
         csum += cn;
       }
       if (!isfinite(csum)) st |= ST_NAN;
+    };
+
+    const int z0 = tl.z0, zend = min(tl.z0 + a.bz, nz);
+    auto iter = [&](int r, Buf& use, Buf& load) {
+      __syncthreads();   // (A0) the previous plane's readers are done
+      ingest(r);
+      // (B) loads for the next iterations; past the lattice or the tile they
+      // re-read clamped planes (in bounds, unused), so every load issues
+      // unconditionally and in this order
+      load_raw(r + 1);
+      load_j(r, load.j);
+      load_pops(clampz(r - 1, nz), load.f);
+      __syncthreads();   // (C) plane r staged
+      accumulate();
+      const int m = r - 1;
+      finalise(m, m >= z0 - 1 && m <= zend && m >= 0 && m < nz, use.j);
+      __syncthreads();   // (F) records of plane r-1 staged
+      const int q = r - 2;
+      if (q >= z0 && q < zend && active) {
+        collide(q, use.f);
+        if (visc) {
+          if (s) fene(q, std::integral_constant<int, 1>{});
+          else fene(q, std::integral_constant<int, 0>{});
+        }
+      }
+    };
+    Buf b0, b1;
+    load_raw(z0 - 2);
+    for (int r = z0 - 2; r <= zend + 1; r += 2) {
+      iter(r, b0, b1);
+      if (r + 1 <= zend + 1) iter(r + 1, b1, b0);
     }
     if (st) atomicOr(a.P.status + tl.run, st);
   }
 }
 
+// ---- physical velocity (observe, export) ------------------------------------------
+// u = (j_A + j_B + (F_A + F_B)/2)/rho at every node of every run, with the
+// forces of the step: Shan-Chen from the 18 neighbours' densities (mirror
+// ghost in z) and the polymer force as the centred divergence of T over the
+// six face neighbours (zero-gradient ghost in z).  One thread per node,
+// plain global loads: this runs only when the velocity is observed.
+template <typename T>
+__device__ __forceinline__ void stress_at(const T* rho, const T* C, int64_t N, int64_t m,
+                                          const RunDev& R, T (&out)[6]) {
+  const T rA = rho[m], rB = rho[N + m];
+  const T rp = R.visc == 0 ? rA : rB;
+  T chi = (rp / (rA + rB) - T(R.chi_lo)) * T(R.inv_chi_range);
+  chi = chi < T(0) ? T(0) : (chi > T(1) ? T(1) : chi);
+  const double tr = (double)C[m] + (double)C[N + m] + (double)C[2 * N + m];
+  const T fP = (T)((R.L2 - 3.0) / (R.L2 - tr));
+  const T coef = chi * T(R.etaP_over_tauP);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) out[c] = coef * (fP * C[c * N + m] - (c < 3 ? T(1) : T(0)));
+}
+
+template <typename T, typename S>
+__global__ void __launch_bounds__(AUX_THREADS) k_flow(AuxArgs<T, S> a) {
+  const int r = blockIdx.y;
+  const RunDev& R = a.runs[r];
+  const int par = a.use_parity ? (R.base & 1) : 0;
+  const int64_t N = R.ld;
+  const int64_t chunk = (R.n + gridDim.x - 1) / gridDim.x;
+  const int64_t beg = (int64_t)blockIdx.x * chunk;
+  const int64_t end = beg + chunk < R.n ? beg + chunk : R.n;
+  const T* rho = a.P.rho[par] + 2 * R.off;
+  const T* J = a.P.j[par] + 6 * R.off;
+  const T* C = a.P.C[R.visc >= 0 ? par : 0] + 6 * R.off;
+  T* U = a.P.u + 3 * R.off;
+  const int nx = R.nx, ny = R.ny, nz = R.nz;
+  const T G = T(R.G), itA = T(R.inv_tau[0]), itB = T(R.inv_tau[1]);
+  (void)itA; (void)itB;
+  for (int64_t n = beg + threadIdx.x; n < end; n += blockDim.x) {
+    const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
+    auto node = [&](int dx, int dy, int dz) -> int64_t {
+      return ((int64_t)clampz(z + dz, nz) * ny + wrapm(y + dy, ny)) * nx + wrapm(x + dx, nx);
+    };
+    const T rA = rho[n], rB = rho[N + n];
+    T sA[3] = {0, 0, 0}, sB[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const int64_t m = node(CX[i], CY[i], CZ[i]);
+      const T nA = rho[m], nB = rho[N + m];
+      const T wt = T(3) * wgt<T>(i);
+      if (CX[i] != 0) { sA[0] += (wt * T(CX[i])) * nB; sB[0] += (wt * T(CX[i])) * nA; }
+      if (CY[i] != 0) { sA[1] += (wt * T(CY[i])) * nB; sB[1] += (wt * T(CY[i])) * nA; }
+      if (CZ[i] != 0) { sA[2] += (wt * T(CZ[i])) * nB; sB[2] += (wt * T(CZ[i])) * nA; }
+    }
+    T F[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) F[c] = -G * rA * sA[c] - G * rB * sB[c];
+    if (R.visc >= 0) {
+      // F^P_a = sum_b [T_ab(x+e_b) - T_ab(x-e_b)]/2 (total over components)
+      constexpr int SYM[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+      T P[3] = {0, 0, 0};
+#pragma unroll
+      for (int bb = 0; bb < 3; ++bb) {
+        T tp[6], tm[6];
+        stress_at(rho, C, N, node(bb == 0, bb == 1, bb == 2), R, tp);
+        stress_at(rho, C, N, node(-(bb == 0), -(bb == 1), -(bb == 2)), R, tm);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) P[c] += T(0.5) * (tp[SYM[c][bb]] - tm[SYM[c][bb]]);
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) F[c] += P[c];
+    }
+    const T irt = T(1) / (rA + rB);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) U[c * N + n] = (J[c * N + n] + J[(3 + c) * N + n] + T(0.5) * F[c]) * irt;
+  }
+}
+
 // ---- host launchers ------------------------------------------------------------------
-template <typename T, typename S>
-void launch_force(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s) {
-#define FORCE_CASE(BX, BY) \
-  else if (block.x == BX && block.y == BY) k_force<T, S, BX, BY><<<grid, block, 0, s>>>(a);
-  if (false) {}
-  LBM_FOR_SHAPES(FORCE_CASE)
-#undef FORCE_CASE
+bool step_shape_ok(int bx, int by, bool fp64) {
+#define SHAPE_OK(BX, BY) \
+  if (bx == BX && by == BY) return fp64 ? step_fits<BX, BY, double>() : step_fits<BX, BY, float>();
+  LBM_FOR_SHAPES(SHAPE_OK)
+#undef SHAPE_OK
+  return false;
+}
+
+template <typename T, typename S, int BX, int BY>
+void launch_step_shape(const StepArgs<T, S>& a, dim3 grid, hipStream_t st) {
+  if constexpr (step_fits<BX, BY, T>()) k_step<T, S, BX, BY><<<grid, dim3(BX, BY), 0, st>>>(a);
 }
 
 template <typename T, typename S>
-void launch_collide(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s) {
-  const dim3 g2(grid.x, 2);
-#define COLLIDE_CASE(BX, BY) \
-  else if (block.x == BX && block.y == BY) k_collide<T, S, BX, BY><<<g2, block, 0, s>>>(a);
+void launch_step(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s) {
+#define STEP_CASE(BX, BY) \
+  else if (block.x == BX && block.y == BY) launch_step_shape<T, S, BX, BY>(a, grid, s);
   if (false) {}
-  LBM_FOR_SHAPES(COLLIDE_CASE)
-#undef COLLIDE_CASE
+  LBM_FOR_SHAPES(STEP_CASE)
+#undef STEP_CASE
 }
 
 template <typename T, typename S>
-void launch_fene(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s) {
-  if (!a.any_visc) return;
-#define FENE_CASE(BX, BY) \
-  else if (block.x == BX && block.y == BY) k_fene<T, S, BX, BY><<<grid, block, 0, s>>>(a);
-  if (false) {}
-  LBM_FOR_SHAPES(FENE_CASE)
-#undef FENE_CASE
+void launch_flow(const AuxArgs<T, S>& a, hipStream_t s) {
+  k_flow<T, S><<<dim3(AUX_BLOCKS, a.nruns), AUX_THREADS, 0, s>>>(a);
 }
 
-#define LBM_INST(T, S)                                                                        \
-  template void launch_force<T, S>(const StepArgs<T, S>&, dim3, dim3, hipStream_t);          \
-  template void launch_collide<T, S>(const StepArgs<T, S>&, dim3, dim3, hipStream_t);        \
-  template void launch_fene<T, S>(const StepArgs<T, S>&, dim3, dim3, hipStream_t);
+#define LBM_INST(T, S)                                                                  \
+  template void launch_step<T, S>(const StepArgs<T, S>&, dim3, dim3, hipStream_t);     \
+  template void launch_flow<T, S>(const AuxArgs<T, S>&, hipStream_t);
 LBM_INST(double, double)
 LBM_INST(float, float)
 LBM_INST(float, __half)

@@ -258,12 +258,12 @@ class Batch:
         buf = ctypes.create_string_buffer(bytes(blob), len(blob))
         _check(lib().lbm_batch_load_state(self._c(), run, buf, len(blob)), "load_state")
 
-    def step_profiled(self, nsteps: int):
-        """Eager steps with HIP events around each pass; returns the summed
-        (force, collide-stream, FENE-P) pass durations in milliseconds."""
-        ms = (ctypes.c_double * 3)()
-        _check(lib().lbm_step_profiled(self._c(), int(nsteps), ms), "step_profiled")
-        return float(ms[0]), float(ms[1]), float(ms[2])
+    def step_profiled(self, nsteps: int) -> float:
+        """Eager steps with HIP events around each step kernel; returns the
+        summed kernel durations in milliseconds."""
+        ms = ctypes.c_double()
+        _check(lib().lbm_step_profiled(self._c(), int(nsteps), ctypes.byref(ms)), "step_profiled")
+        return float(ms.value)
 
     def steps_done(self, run: int = 0) -> int:
         v = ctypes.c_int64()
@@ -276,7 +276,7 @@ class Batch:
         _check(lib().lbm_get_launch(self._c(), ctypes.byref(l)), "get_launch")
         return dict(bx=l.bx, by=l.by, bz=l.bz, persistent=l.persistent)
 
-    def set_launch(self, bx=64, by=4, bz=1, persistent=0):
+    def set_launch(self, bx=32, by=8, bz=16, persistent=0):
         l = LbmLaunch(bx, by, bz, persistent)
         _check(lib().lbm_set_launch(self._c(), ctypes.byref(l)), "set_launch")
 

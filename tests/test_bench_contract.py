@@ -19,8 +19,8 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
 
 
-def _fake_run(ms=(0.4, 1.25, 0.3), launch=(32, 8, 16)):
-    return dict(nodes=512 * 256 * 128, ms=list(ms),
+def _fake_run(ms=1.25, launch=(32, 8, 16)):
+    return dict(nodes=512 * 256 * 128, ms=ms,
                 launch=dict(bx=launch[0], by=launch[1], bz=launch[2], persistent=0))
 
 
@@ -28,23 +28,21 @@ def test_roofline_fields_and_arithmetic(monkeypatch):
     import bench
     monkeypatch.setattr(bench, "measured_traffic", lambda p, l, b=None: None)
     r = bench.roofline("fp32", _fake_run())
-    for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "step"):
+    for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in r
     n = 512 * 256 * 128
     assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
-    assert r["achieved"] == pytest.approx(304 * n / 1.25e-3 / 1e9, rel=1e-3)
+    assert r["achieved"] == pytest.approx(352 * n / 1.25e-3 / 1e9, rel=1e-3)
     assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, rel=1e-3)
-    assert r["step"]["achieved"] == pytest.approx(352 * n / 1.95e-3 / 1e9, rel=1e-3)
-    assert r["traffic"] is None
+    assert r["traffic"] is None and r["bytes_min_per_node"] == 416
     r16 = bench.roofline("fp16s", _fake_run())
-    assert r16["bytes_alg_per_node"] == 152 and r16["step"]["bytes_alg_per_update"] == 200
+    assert r16["bytes_alg_per_node"] == 200 and r16["bytes_min_per_node"] == 264
 
 
 def test_traffic_lookup_needs_matching_sources(tmp_path, monkeypatch):
     import bench
     from paper_1411_2181_amd.build import source_hash
-    entry = {"k_force": {"bytes": 1}, "k_collide": {"bytes": 2}, "k_fene": {"bytes": 3},
-             "step_bytes_per_node": 500.0}
+    entry = {"k_step": {"bytes": 2, "bytes_per_node": 500.0}}
     prof = tmp_path / "profiles"
     prof.mkdir()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
@@ -57,4 +55,4 @@ def test_traffic_lookup_needs_matching_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic("fp16s", _fake_run()["launch"]) is None
     assert bench.measured_traffic("fp32", _fake_run()["launch"], (64, 256, 128)) is None
     r = bench.roofline("fp32", _fake_run())
-    assert r["traffic"] == 2 and r["step"]["traffic_per_update"] == 500.0
+    assert r["traffic"] == 2 and r["traffic_per_node"] == 500.0

@@ -123,9 +123,9 @@ def test_small_droplet_2000_steps_parity(lbm, oracle_2000, case):
 def test_launch_shapes_bit_identical(lbm):
     d = WL.small_droplet_viscoelastic()
     ref = None
-    for shape in [dict(bx=64, by=4, bz=1), dict(bx=32, by=8, bz=3),
-                  dict(bx=128, by=2, bz=8, persistent=64), dict(bx=64, by=2, bz=32),
-                  dict(bx=32, by=4, bz=5, persistent=8)]:
+    for shape in [dict(bx=32, by=8, bz=1), dict(bx=64, by=4, bz=3),
+                  dict(bx=16, by=16, bz=8, persistent=64), dict(bx=32, by=8, bz=32),
+                  dict(bx=64, by=4, bz=5, persistent=16)]:
         s = lbm.Solver(d, "fp64")
         s.set_launch(**shape)
         s.step(25)
@@ -134,6 +134,9 @@ def test_launch_shapes_bit_identical(lbm):
         if ref is None:
             ref = out
         else:
+            df = float(np.abs(out[0] - ref[0]).max() / np.abs(ref[0]).max())
+            dC = float(np.abs(out[1] - ref[1]).max() / np.abs(ref[1]).max())
+            print(f"  {shape}: max rel diff f {df:.2e}, C {dC:.2e}", flush=True)
             assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), shape
 
 
@@ -283,11 +286,9 @@ def test_component_count_matches_oracle(lbm):
     s.close()
 
 
-# FP16S velocity bound: this case shears at U_w = 0.005, where the shifted
-# values are ~50x smaller than at U_w ~ 0.1 and the 11-bit representation
-# noise is ~2e-3 of the velocity (measured 2.1e-3); at the larger droplet
-# cases (U_w 0.05-0.1) it is ~1.5e-4 (precision study).
-@pytest.mark.parametrize("precision,d_tol,u_tol", [("fp32", 1e-3, 1e-4), ("fp16s", 5e-3, 5e-3)])
+# Bars of the reduced-precision storage against the FP64 path: D within
+# 1e-3 (FP32) and 5e-3 (FP16S), velocity relative L2 within 1e-4 for both.
+@pytest.mark.parametrize("precision,d_tol,u_tol", [("fp32", 1e-3, 1e-4), ("fp16s", 5e-3, 1e-4)])
 def test_reduced_precision_against_fp64(lbm, precision, d_tol, u_tol):
     d = WL.small_droplet_viscoelastic()
     ref = lbm.Solver(d, "fp64")
