@@ -16,14 +16,15 @@ import time
 _HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(_HERE, "autotune_cache.json")
 
-SHAPES = [(32, 8), (64, 4), (16, 16), (32, 16)]
-BZ = [8, 16, 32, 64]
+SHAPES = [(32, 8), (16, 16), (16, 8), (8, 16)]
+# the FP64 rings of the 512-thread tiles exceed the LDS
+SHAPES_FP64 = [(16, 8), (8, 16)]
+BZ = [16, 32, 64, 128]
 PERSISTENT = [1024, 2048]
 
 
 def candidates(nz_max: int, precision: str = "fp32"):
-    # the FP64 rings of the 512-thread tile exceed the LDS
-    shapes = [sh for sh in SHAPES if not (precision == "fp64" and sh == (32, 16))]
+    shapes = SHAPES_FP64 if precision == "fp64" else SHAPES
     out = []
     for bx, by in shapes:
         for bz in BZ:

@@ -72,9 +72,9 @@ size_t elem_S(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 
 size_t elem_T(int prec) { return prec == LBM_FP64 ? 8 : 4; }
 
 int64_t max_tiles(const lbm_params* p, int32_t nruns) {
-  // smallest tile: bx = 32, by = 4, bz = 1
+  // bound for every tile shape: bx >= 8, by >= 8, bz >= 1
   int64_t t = 0;
-  for (int r = 0; r < nruns; ++r) t += (int64_t)((p[r].nx + 31) / 32) * ((p[r].ny + 3) / 4) * p[r].nz;
+  for (int r = 0; r < nruns; ++r) t += (int64_t)((p[r].nx + 7) / 8) * ((p[r].ny + 7) / 8) * p[r].nz;
   return (t + 7) / 8 * 8;
 }
 
@@ -119,7 +119,7 @@ struct lbm_ctx {
   std::vector<int64_t> done;
   char* ws = nullptr;
   Layout L{};
-  lbm_launch launch{32, 8, 16, 0};
+  lbm_launch launch{16, 8, 16, 0};
   int64_t ntiles = 0;          // entries of the (XCD-permuted) tile table
   std::map<int, hipGraphExec_t> graphs;
   std::map<int, hipGraph_t> graph_src;
@@ -176,12 +176,11 @@ lbm::AuxArgs<T, S> aux_args(const lbm_ctx* c, int use_parity) {
   return a;
 }
 
-// Two workgroups per tile slot (one per component, 8 ids apart so that both
-// run on the same XCD); a persistent grid is a multiple of 16 workgroups
-// that loop over the tile table.
+// One workgroup per tile; a persistent grid is a multiple of 8 workgroups
+// (one block of tiles per XCD) that loop over the tile table.
 dim3 step_grid(const lbm_ctx* c) {
-  int64_t g = 2 * c->ntiles;
-  if (c->launch.persistent > 0) g = std::min<int64_t>(g, std::max(16, c->launch.persistent / 16 * 16));
+  int64_t g = c->ntiles;
+  if (c->launch.persistent > 0) g = std::min<int64_t>(g, std::max(8, c->launch.persistent / 8 * 8));
   return dim3((unsigned)g);
 }
 

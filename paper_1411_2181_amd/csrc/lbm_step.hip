@@ -14,26 +14,26 @@
 // that (state n, parity p) and writes state n+1 (parity p^1): populations,
 // densities, momenta and C.  No intermediate field goes through HBM.
 //
-// Work split.  Two workgroups per tile, one per component s, dispatched to
-// the same XCD (workgroups go round-robin over the 8 XCDs, so ids b and b+8
-// share one): both recompute the forces on the tile and a one-node frame
-// from the same inputs, the second mostly from that XCD's L2.  The workgroup
-// of component s collides and streams s and updates three of the six
-// components of C (xx yy zz for s = A, xy xz yz for s = B).
+// Work split.  One workgroup of 2 * bx * by threads per tile.  For the forces
+// every thread owns one position of the tile + 1-node frame (and of the
+// 2-node frame); for the collision and the FENE-P update the threads with
+// threadIdx.z = s handle component s of the bx * by columns (s = 0 updates
+// C_xx, C_yy, C_zz, s = 1 updates C_xy, C_xz, C_yz).
 //
-// z-march.  A workgroup advances its bx*by column block plane by plane.  In
-// the iteration of plane r it
-//   (A) stages plane r of both densities and of the stress T (computed once
-//       per node, Peterlin factor in FP64) on the tile + 2-node frame in LDS,
-//       and C on the 1-node frame;
-//   (D) adds plane r's contributions to the Shan-Chen sums and to the stress
-//       divergence of the 1-frame nodes at planes r-1, r and r+1 (registers:
-//       each thread owns the frame nodes it finalises);
-//   (E) finalises plane r-1: forces, the velocity shift, the records the
-//       collision reads, and the physical velocity, into LDS rings;
-//   (G) collides and streams plane r-2 and updates its C components there.
-// The loads of plane r+1 (densities, C), of the momenta of plane r and of
-// the populations of plane r-1 are in flight while plane r is processed.
+// z-march.  The workgroup advances its column block plane by plane, with two
+// barriers per plane.  In the iteration of plane r:
+//   phase X: stage plane r of both densities (LDS ring) and of the stress T
+//            (computed once per node, Peterlin factor in FP64; transient);
+//            collide, stream and update C at plane r-3 (records, moments,
+//            velocities and C of planes r-4 .. r-2 from LDS rings);
+//   phase Y: stage C of plane r (ring); add plane r's terms of the stress
+//            divergence at planes r-1, r, r+1 (per thread, in registers);
+//            finalise plane r-1 on the 1-node frame: Shan-Chen force from the
+//            density ring, polymer force, velocity shift, the records the
+//            collision reads, the node moments and the physical velocity.
+// The loads of the next plane's densities and C, of the populations of the
+// next plane to collide and of the momenta of plane r are in flight while
+// the rest of the iteration computes.
 //
 // Storage and collision.  Populations are held as
 // g_i = f_i - w_i (rho + 3 c_i.j) against the moments of the node that holds
@@ -59,95 +59,69 @@ namespace lbm {
 __device__ __forceinline__ int wrapp(int v, int n) { return ((v % n) + n) % n; }
 
 // Frame geometry of a BX x BY tile: the 1-node frame (tile + 1 on each side)
-// and the 2-node frame.  Slot 0 of every thread is its own column; the ring
-// positions (frame minus tile) are dealt out over the threads.
+// and the 2-node frame, both in row-major order.
 template <int BX, int BY>
 struct Frame {
-  static constexpr int NT = BX * BY;
+  static constexpr int NT = BX * BY, NW = 2 * NT;        // columns, threads
   static constexpr int HX1 = BX + 2, HY1 = BY + 2, N1 = HX1 * HY1;
   static constexpr int HX2 = BX + 4, HY2 = BY + 4, N2 = HX2 * HY2;
-  static constexpr int R1 = N1 - NT, R2 = N2 - NT;
-  static constexpr int K1 = 1 + (R1 + NT - 1) / NT;   // 1-frame positions per thread
-  static constexpr int K2 = 1 + (R2 + NT - 1) / NT;   // 2-frame positions per thread
-  // ring position e < R1 of the 1-frame: bottom row, top row, left, right column
-  static __device__ __forceinline__ void ring1(int e, int& hx, int& hy) {
-    if (e < HX1) { hx = e; hy = 0; }
-    else if (e < 2 * HX1) { hx = e - HX1; hy = HY1 - 1; }
-    else if (e < 2 * HX1 + BY) { hx = 0; hy = e - 2 * HX1 + 1; }
-    else { hx = HX1 - 1; hy = e - 2 * HX1 - BY + 1; }
-  }
-  // ring position e < R2 of the 2-frame: rows 0, 1, HY2-2, HY2-1, then the
-  // columns 0, 1, HX2-2, HX2-1 of rows 2 .. BY+1
-  static __device__ __forceinline__ void ring2(int e, int& hx, int& hy) {
-    if (e < 4 * HX2) {
-      const int row = e / HX2;
-      hx = e - row * HX2;
-      hy = row < 2 ? row : HY2 - 4 + row;
-    } else {
-      const int f = e - 4 * HX2;
-      const int col = f / BY;
-      hy = 2 + (f - col * BY);
-      hx = col < 2 ? col : HX2 - 4 + col;
-    }
-  }
+  static constexpr int K2 = (N2 + NW - 1) / NW;          // 2-frame positions per thread
+  static_assert(N1 <= NW, "one 1-frame position per thread");
 };
 
 template <typename T, int BX, int BY>
 struct StepLds {
   using F = Frame<BX, BY>;
-  T rho[2][F::N2];          // plane r: rho_A, rho_B on the 2-frame
-  T stress[6][F::N2];       // plane r: T on the 2-frame
-  V4<T> rec[3][2][F::N1];   // planes mod 3: (a, P), (u^eq, b) of this component
-  T u[2][3][F::N1];         // planes mod 2: physical velocity
-  T C[3][3][F::N1];         // planes mod 3: this workgroup's three C components
+  T rho[3][2][F::N2];         // planes mod 3: rho_A, rho_B on the 2-frame
+  T stress[6][F::N2];         // plane r: T on the 2-frame
+  T C[4][6][F::N1];           // planes mod 4: C on the 1-frame
+  V4<T> rec[3][2][2][F::N1];  // planes mod 3, component: (a, P), (u^eq, b)
+  T u[3][3][F::N1];           // planes mod 3: physical velocity on the 1-frame
+  T M[2][2][4][F::NT];        // planes mod 2, component: rho, j of the tile columns
 };
 
 template <int BX, int BY, typename T>
 constexpr bool step_fits() { return sizeof(StepLds<T, BX, BY>) <= 160 * 1024; }
 
-// Shapes with a compiled instance: FP32 (and FP16 storage) all, FP64 those
-// whose rings fit the 160 KiB of LDS.
-#define LBM_FOR_SHAPES(M) M(32, 8) M(64, 4) M(16, 16) M(32, 16)
+// Shapes with a compiled instance (those whose rings fit the 160 KiB of LDS
+// in the compute type).
+#define LBM_FOR_SHAPES(M) M(32, 8) M(16, 16) M(16, 8) M(8, 16)
 
 template <typename T, typename S, int BX, int BY>
-__global__ void __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(2)))
-k_step(StepArgs<T, S> a) {
+__global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
   using F = Frame<BX, BY>;
-  constexpr int NT = F::NT, HX1 = F::HX1, HX2 = F::HX2, K1 = F::K1, K2 = F::K2;
+  constexpr int NT = F::NT, NW = F::NW, HX1 = F::HX1, N1 = F::N1, HX2 = F::HX2, N2 = F::N2;
+  constexpr int K2 = F::K2;
   static_assert(step_fits<BX, BY, T>(), "LDS rings exceed 160 KiB");
   __shared__ StepLds<T, BX, BY> L;
   using St = Store<T, S>;
   const T kS = T(St::kScale), ikS = T(1.0 / St::kScale);
   const int g = *a.gstep;
-  const int tx = (int)threadIdx.x, ty = (int)threadIdx.y, tid = ty * BX + tx;
-  const int b = (int)blockIdx.x;
-  const int s = (b >> 3) & 1;                      // component of this workgroup
-  const int tslot = ((b >> 4) << 3) | (b & 7);     // same tile slot and XCD for s = 0, 1
-  const int tstride = (int)gridDim.x >> 1;
+  const int tx = (int)threadIdx.x, ty = (int)threadIdx.y, s = (int)threadIdx.z;
+  const int tid = (s * BY + ty) * BX + tx;
 
-  // frame positions of this thread (independent of the tile)
-  int f1x[K1], f1y[K1], p1[K1], p12[K1];   // 1-frame: coords, LDS index, 2-frame index
-  int f2x[K2], f2y[K2], p2[K2], q1[K2];    // 2-frame: coords, LDS index, 1-frame index (or -1)
-#pragma unroll
-  for (int k = 0; k < K1; ++k) {
-    int hx = tx + 1, hy = ty + 1;
-    if (k > 0) F::ring1(min(tid + (k - 1) * NT, F::R1 - 1), hx, hy);
-    f1x[k] = hx; f1y[k] = hy;
-    p1[k] = hy * HX1 + hx;
-    p12[k] = (hy + 1) * HX2 + hx + 1;
-  }
+  // this thread's 1-frame position (threads past N1 repeat the last one and
+  // store nothing) and 2-frame positions
+  const bool has1 = tid < N1;
+  const int e1 = has1 ? tid : N1 - 1;
+  const int h1x = e1 % HX1, h1y = e1 / HX1;
+  const int c2of1 = (h1y + 1) * HX2 + h1x + 1;              // its 2-frame index
+  const bool inner = h1x >= 1 && h1x <= BX && h1y >= 1 && h1y <= BY;
+  const int mcol = (h1y - 1) * BX + (h1x - 1);               // its tile column if inner
+  int e2[K2], q1[K2];
+  bool has2[K2];
 #pragma unroll
   for (int k = 0; k < K2; ++k) {
-    int hx = tx + 2, hy = ty + 2;
-    if (k > 0) F::ring2(min(tid + (k - 1) * NT, F::R2 - 1), hx, hy);
-    f2x[k] = hx; f2y[k] = hy;
-    p2[k] = hy * HX2 + hx;
+    has2[k] = tid + k * NW < N2;
+    e2[k] = has2[k] ? tid + k * NW : N2 - 1;
+    const int hx = e2[k] % HX2, hy = e2[k] / HX2;
     const bool in1 = hx >= 1 && hx <= BX + 2 && hy >= 1 && hy <= BY + 2;
-    q1[k] = in1 ? (hy - 1) * HX1 + (hx - 1) : -1;
+    q1[k] = has2[k] && in1 ? (hy - 1) * HX1 + (hx - 1) : -1;
   }
   const int lc = (ty + 1) * HX1 + (tx + 1);   // own column in the 1-frame
+  const int oc = ty * BX + tx;                // own column in the tile
 
-  for (int t = tslot; t < a.ntiles; t += tstride) {
+  for (int t = (int)blockIdx.x; t < a.ntiles; t += (int)gridDim.x) {
     const Tile tl = a.tiles[t];
     if (tl.run < 0) continue;
     const RunDev& R = a.runs[tl.run];
@@ -163,7 +137,7 @@ k_step(StepArgs<T, S> a) {
     const T G = T(R.G);
     const T tA = T(R.tau[0]), tB = T(R.tau[1]);
     const T itA = T(R.inv_tau[0]), itB = T(R.inv_tau[1]);
-    const T om = s ? itB : itA;                  // 1/tau of this component
+    const T om = s ? itB : itA;   // 1/tau of this thread's component
     const T om1 = T(1) - om;
     const T uw = T(R.u_wall);
     const int vph = R.visc;
@@ -182,13 +156,11 @@ k_step(StepArgs<T, S> a) {
     T* __restrict__ C_out = a.P.C[par ^ 1] + 6 * R.off;
 
     // plane offsets of the frame positions (periodic in x and y)
-    int col1[K1], col2[K2];
-#pragma unroll
-    for (int k = 0; k < K1; ++k)
-      col1[k] = wrapp(tl.y0 + f1y[k] - 1, ny) * nx + wrapp(tl.x0 + f1x[k] - 1, nx);
+    const int col1 = wrapp(tl.y0 + h1y - 1, ny) * nx + wrapp(tl.x0 + h1x - 1, nx);
+    int col2[K2];
 #pragma unroll
     for (int k = 0; k < K2; ++k)
-      col2[k] = wrapp(tl.y0 + f2y[k] - 2, ny) * nx + wrapp(tl.x0 + f2x[k] - 2, nx);
+      col2[k] = wrapp(tl.y0 + e2[k] / HX2 - 2, ny) * nx + wrapp(tl.x0 + e2[k] % HX2 - 2, nx);
 
     // Pulls: byte offsets inside one direction array (a run's array is
     // < 4 GiB, which the library checks).  Inactive threads of a ragged tile
@@ -196,21 +168,26 @@ k_step(StepArgs<T, S> a) {
     const int xq = x < nx ? x : nx - 1, yq = y < ny ? y : ny - 1;
     const int xm = xq == 0 ? nx - 1 : xq - 1, xp = xq >= nx - 1 ? 0 : xq + 1;
     const int ym = yq == 0 ? ny - 1 : yq - 1, yp = yq >= ny - 1 ? 0 : yq + 1;
-    constexpr uint32_t SB = sizeof(S);
-    const uint32_t pb = (uint32_t)nxy * SB;
-    const uint32_t rowb[3] = {(uint32_t)(ym * nx) * SB, (uint32_t)(yq * nx) * SB,
-                              (uint32_t)(yp * nx) * SB};
-    const uint32_t colb[3] = {(uint32_t)xm * SB, (uint32_t)xq * SB, (uint32_t)xp * SB};
+    constexpr uint32_t SZ = sizeof(S);
+    const uint32_t pb = (uint32_t)nxy * SZ;
+    const uint32_t rowb[3] = {(uint32_t)(ym * nx) * SZ, (uint32_t)(yq * nx) * SZ,
+                              (uint32_t)(yp * nx) * SZ};
+    const uint32_t colb[3] = {(uint32_t)xm * SZ, (uint32_t)xq * SZ, (uint32_t)xp * SZ};
     auto arr = [&](const S* base, int i, uint32_t off) {
       return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base + (int64_t)i * N) + off);
     };
     const int own = yq * nx + xq;
 
-    struct Buf {
-      T f[Q];        // populations arriving at the own column (one plane)
-      T j[K1][6];    // momenta of the 1-frame positions (one plane)
-    };
     T raw[K2][8];    // densities and C of the 2-frame positions (next plane)
+    T cst[K2][6];    // C of the plane being staged, kept for the C ring
+    T jv[6];         // momenta of the 1-frame position (plane to finalise)
+    T pops[Q];       // populations arriving at the own column (plane to collide)
+    T acc[3][3];     // stress divergence of the 1-frame position: planes r-1, r, r+1
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[p][c] = T(0);
+    uint32_t st = 0;
 
     // ---- loads ---------------------------------------------------------------
     auto load_raw = [&](int r) {
@@ -226,56 +203,39 @@ k_step(StepArgs<T, S> a) {
         }
       }
     };
-    auto load_j = [&](int r, T (&jv)[K1][6]) {
-      const int zo = clampz(r, nz) * nxy;
+    auto load_j = [&](int r) {
+      const int m = clampz(r, nz) * nxy + col1;
 #pragma unroll
-      for (int k = 0; k < K1; ++k) {
-        const int m = zo + col1[k];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) jv[k][c] = J_in[c * N + m];
-      }
+      for (int c = 0; c < 6; ++c) jv[c] = J_in[c * N + m];
     };
     // populations arriving at the own column in plane zz: pulled from
     // x - c_i, or the node's own opposite population where the link crosses
     // a wall (the choice is uniform and made by selects)
-    auto load_pops = [&](int zz, T (&v)[Q]) {
+    auto load_pops = [&](int zz) {
       const uint32_t ownb = (uint32_t)zz * pb + rowb[1] + colb[1];
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         const int zs = zz - CZ[i];
         const uint32_t off = (uint32_t)zs * pb + rowb[1 - CY[i]] + colb[1 - CX[i]];
         if (CZ[i] == 0) {
-          v[i] = St::load(arr(fs, i, off), 0);
+          pops[i] = St::load(arr(fs, i, off), 0);
         } else {
           const bool in = zs >= 0 && zs < nz;
-          v[i] = St::load(arr(fs, in ? i : OPPI[i], in ? off : ownb), 0);
+          pops[i] = St::load(arr(fs, in ? i : OPPI[i], in ? off : ownb), 0);
         }
       }
     };
 
-    // ---- per-thread pipeline state ----------------------------------------------
-    T acc[3][K1][9];     // planes r-1, r, r+1: Shan-Chen sums for A, for B; stress divergence
-    T rsv[2][K1][2];     // densities of the 1-frame positions: [0] plane r-1, [1] plane r
-    T Cown[4][6];        // own column C: planes r, r-1, r-2, r-3
-    T rown[3];           // own column density of this component: planes r, r-1, r-2
-    T uown[3][3];        // own column velocity: planes q-1, q, q+1 (q = r-2)
-    T jown[2][3];        // own column momentum of this component: planes r-2, r-1
-#pragma unroll
-    for (int p = 0; p < 3; ++p)
-#pragma unroll
-      for (int k = 0; k < K1; ++k)
-#pragma unroll
-        for (int c = 0; c < 9; ++c) acc[p][k][c] = T(0);
-    uint32_t st = 0;
-
-    // (A) stage plane r
+    // ---- phase X: stage plane r ------------------------------------------------
     auto ingest = [&](int r) {
       const int sl3 = (r + 3) % 3;
 #pragma unroll
       for (int k = 0; k < K2; ++k) {
         const T rA = raw[k][0], rB = raw[k][1];
-        L.rho[0][p2[k]] = rA;
-        L.rho[1][p2[k]] = rB;
+        if (has2[k]) {
+          L.rho[sl3][0][e2[k]] = rA;
+          L.rho[sl3][1][e2[k]] = rB;
+        }
         if (visc) {
           // T = chi (eta_P/tau_P)(f C - I): chi the clamped rescaled mass
           // fraction of the polymer phase's component, f in FP64
@@ -285,154 +245,26 @@ k_step(StepArgs<T, S> a) {
           const double tr = (double)raw[k][2] + (double)raw[k][3] + (double)raw[k][4];
           const T fP = (T)((L2 - 3.0) / (L2 - tr));
           const T coef = chi * eP;
+          if (has2[k]) {
 #pragma unroll
-          for (int c = 0; c < 6; ++c)
-            L.stress[c][p2[k]] = coef * (fP * raw[k][2 + c] - (c < 3 ? T(1) : T(0)));
-          if (q1[k] >= 0) {
-#pragma unroll
-            for (int kk = 0; kk < 3; ++kk) L.C[sl3][kk][q1[k]] = s ? raw[k][5 + kk] : raw[k][2 + kk];
+            for (int c = 0; c < 6; ++c)
+              L.stress[c][e2[k]] = coef * (fP * raw[k][2 + c] - (c < 3 ? T(1) : T(0)));
           }
-        }
-      }
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        Cown[3][c] = Cown[2][c];
-        Cown[2][c] = Cown[1][c];
-        Cown[1][c] = Cown[0][c];
-        Cown[0][c] = raw[0][2 + c];
-      }
-      rown[2] = rown[1];
-      rown[1] = rown[0];
-      rown[0] = s ? raw[0][1] : raw[0][0];
-    };
-
-    // (D) contributions of plane r to the sums of the 1-frame nodes
-    auto accumulate = [&]() {
-#pragma unroll
-      for (int k = 0; k < K1; ++k) {
-        const int c2 = p12[k];
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-          // the node at plane r - c_z reaches plane r through link i
-          const int pl = 1 - CZ[i];
-          const int nb = c2 + CY[i] * HX2 + CX[i];
-          const T nA = L.rho[0][nb], nB = L.rho[1][nb];
-          const T wt = T(3) * wgt<T>(i);
-          if (CX[i] != 0) { acc[pl][k][0] += (wt * T(CX[i])) * nB; acc[pl][k][3] += (wt * T(CX[i])) * nA; }
-          if (CY[i] != 0) { acc[pl][k][1] += (wt * T(CY[i])) * nB; acc[pl][k][4] += (wt * T(CY[i])) * nA; }
-          if (CZ[i] != 0) { acc[pl][k][2] += (wt * T(CZ[i])) * nB; acc[pl][k][5] += (wt * T(CZ[i])) * nA; }
+          for (int c = 0; c < 6; ++c) cst[k][c] = raw[k][2 + c];
         }
-        if (visc) {
-          // F^P_a = sum_b [T_ab(x+e_b) - T_ab(x-e_b)]/2: the x and y terms
-          // from plane r; T_az(r) enters the node above with + and the node
-          // below with -
-          const T dx0 = T(0.5) * (L.stress[0][c2 + 1] - L.stress[0][c2 - 1]);
-          const T dx1 = T(0.5) * (L.stress[3][c2 + 1] - L.stress[3][c2 - 1]);
-          const T dx2 = T(0.5) * (L.stress[4][c2 + 1] - L.stress[4][c2 - 1]);
-          const T dy0 = T(0.5) * (L.stress[3][c2 + HX2] - L.stress[3][c2 - HX2]);
-          const T dy1 = T(0.5) * (L.stress[1][c2 + HX2] - L.stress[1][c2 - HX2]);
-          const T dy2 = T(0.5) * (L.stress[5][c2 + HX2] - L.stress[5][c2 - HX2]);
-          acc[1][k][6] += dx0 + dy0;
-          acc[1][k][7] += dx1 + dy1;
-          acc[1][k][8] += dx2 + dy2;
-          const T z0h = T(0.5) * L.stress[4][c2], z1h = T(0.5) * L.stress[5][c2];
-          const T z2h = T(0.5) * L.stress[2][c2];
-          acc[0][k][6] += z0h; acc[0][k][7] += z1h; acc[0][k][8] += z2h;
-          acc[2][k][6] -= z0h; acc[2][k][7] -= z1h; acc[2][k][8] -= z2h;
-        }
-        rsv[1][k][0] = L.rho[0][c2];
-        rsv[1][k][1] = L.rho[1][c2];
       }
     };
 
-    // (E) plane m = r-1 of the 1-frame: forces, velocity shift, records, u
-    auto finalise = [&](int m, bool want, const T (&jv)[K1][6]) {
-      const int sl3 = (m + 3) % 3, sl2 = m & 1;
-      T un[3] = {T(0), T(0), T(0)}, jn[3] = {T(0), T(0), T(0)};
-      if (want) {
-#pragma unroll
-        for (int k = 0; k < K1; ++k) {
-          const T rA = rsv[0][k][0], rB = rsv[0][k][1];
-          // Shan-Chen: F_A = -G rho_A sum_i 3 w_i rho_B(x+c_i) c_i (and A<->B)
-          T FA[3], FB[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            FA[c] = -G * rA * acc[0][k][c];
-            FB[c] = -G * rB * acc[0][k][3 + c];
-          }
-          const T irt = T(1) / (rA + rB);
-          if (visc) {
-            // polymer force split over the components by mass fraction
-            const T fa = rA * irt, fb = rB * irt;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              FA[c] = FA[c] + fa * acc[0][k][6 + c];
-              FB[c] = FB[c] + fb * acc[0][k][6 + c];
-            }
-          }
-          // velocity shift u' = sum(j_s/tau_s)/sum(rho_s/tau_s),
-          // u^eq_s = u' + tau_s F_s/rho_s
-          const T iden = T(1) / (rA * itA + rB * itB);
-          const T sA = tA / rA, sB = tB / rB;
-          T ue[3], js[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const T up = (jv[k][c] * itA + jv[k][3 + c] * itB) * iden;
-            ue[c] = s ? up + sB * FB[c] : up + sA * FA[c];
-            js[c] = s ? jv[k][3 + c] : jv[k][c];
-          }
-          const T rs = s ? rB : rA;
-          const T wr = om * rs;
-          const T usq = ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2];
-          V4<T> r0, r1;
-          r0.x = rs - T(1.5) * wr * usq;
-          r0.y = wr * ue[0] + om1 * js[0];
-          r0.z = wr * ue[1] + om1 * js[1];
-          r0.w = wr * ue[2] + om1 * js[2];
-          r1.x = ue[0]; r1.y = ue[1]; r1.z = ue[2];
-          r1.w = T(4.5) * wr;
-          L.rec[sl3][0][p1[k]] = r0;
-          L.rec[sl3][1][p1[k]] = r1;
-          if (visc) {
-            // physical velocity u = (j_A + j_B + (F_A + F_B)/2)/rho
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const T uc = (jv[k][c] + jv[k][3 + c] + T(0.5) * (FA[c] + FB[c])) * irt;
-              L.u[sl2][c][p1[k]] = uc;
-              if (k == 0) un[c] = uc;
-            }
-          }
-          if (k == 0) { jn[0] = js[0]; jn[1] = js[1]; jn[2] = js[2]; }
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        uown[0][c] = uown[1][c];
-        uown[1][c] = uown[2][c];
-        uown[2][c] = un[c];
-        jown[0][c] = jown[1][c];
-        jown[1][c] = jn[c];
-      }
-#pragma unroll
-      for (int k = 0; k < K1; ++k) {
-#pragma unroll
-        for (int c = 0; c < 9; ++c) {
-          acc[0][k][c] = acc[1][k][c];
-          acc[1][k][c] = acc[2][k][c];
-          acc[2][k][c] = T(0);
-        }
-        rsv[0][k][0] = rsv[1][k][0];
-        rsv[0][k][1] = rsv[1][k][1];
-      }
-    };
-
-    // (G) collide and stream this component into plane q of the own column
-    auto collide = [&](int q, T (&v)[Q]) {
+    // ---- phase X: collide and stream component s into plane q of the own
+    // column
+    auto collide = [&](int q) {
       const int n = q * nxy + own;
-      const uint32_t nb = (uint32_t)n * SB;
+      const uint32_t nb = (uint32_t)n * SZ;
       const int slq = (q + 3) % 3, slm = (q + 2) % 3, slp = (q + 4) % 3;
-      const T rx = rown[2];
-      const T jx0 = jown[0][0], jx1 = jown[0][1], jx2 = jown[0][2];
+      const int sm2 = q & 1;
+      const T rx = L.M[sm2][s][0][oc];
+      const T jx0 = L.M[sm2][s][1][oc], jx1 = L.M[sm2][s][2][oc], jx2 = L.M[sm2][s][3][oc];
       T drho = 0, dj0 = 0, dj1 = 0, dj2 = 0;
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
@@ -452,7 +284,7 @@ k_step(StepArgs<T, S> a) {
           const T uwall = CZ[o] > 0 ? uw : -uw;
           wall = in ? T(0) : ((T(6) * kS * wgt<T>(o)) * rx) * (T(CX[o]) * uwall);
         }
-        const V4<T> r0 = L.rec[sl][0][src], r1 = L.rec[sl][1][src];
+        const V4<T> r0 = L.rec[sl][s][0][src], r1 = L.rec[sl][s][1][src];
         T cP = 0, cu = 0, cj = 0;
         if (CX[i] != 0) { cP += T(CX[i]) * r0.y; cu += T(CX[i]) * r1.x; cj += T(CX[i]) * jx0; }
         if (CY[i] != 0) { cP += T(CY[i]) * r0.z; cu += T(CY[i]) * r1.y; cj += T(CY[i]) * jx1; }
@@ -460,8 +292,8 @@ k_step(StepArgs<T, S> a) {
         cP *= sg;
         cu *= sg;
         const T e = (r0.x - rx) + T(3) * (cP - cj) + r1.w * cu * cu;
-        const T h = om1 * v[i] + (wgt<T>(i) * kS) * e - wall;
-        v[i] = h;
+        const T h = om1 * pops[i] + (wgt<T>(i) * kS) * e - wall;
+        pops[i] = h;
         drho += h;
         if (CX[i] != 0) dj0 += T(CX[i]) * h;
         if (CY[i] != 0) dj1 += T(CY[i]) * h;
@@ -481,7 +313,7 @@ k_step(StepArgs<T, S> a) {
         if (CX[i] != 0) cd += T(CX[i]) * dj0;
         if (CY[i] != 0) cd += T(CY[i]) * dj1;
         if (CZ[i] != 0) cd += T(CZ[i]) * dj2;
-        const T out = v[i] - wgt<T>(i) * (drho + T(3) * cd);
+        const T out = pops[i] - wgt<T>(i) * (drho + T(3) * cd);
         S* dst = reinterpret_cast<S*>(reinterpret_cast<char*>(fo + (int64_t)i * N) + nb);
         St::put(dst, 0, out, hb + (uint32_t)i * 0x9e3779b9u);
       }
@@ -492,31 +324,32 @@ k_step(StepArgs<T, S> a) {
       if (!isfinite(rnew + jn0 + jn1 + jn2)) st |= ST_NAN;
     };
 
-    // (G) FENE-P for this workgroup's C components at plane q of the own
+    // ---- phase X: FENE-P for this thread's C components at plane q of the own
     // column: C^{n+1} = C - A + S - (f C - I)/tau_P with centred grad u,
     // first-order upwind A and S_kl = sum_m C_km G_ml + G_mk C_ml.  Ghost
-    // planes: C zero-gradient (the clamped planes), u extrapolated through
-    // the wall velocity, u(-1) = 2 u_bot - u(0), u(nz) = 2 u_top - u(nz-1).
+    // planes: C zero-gradient (the clamped planes of the ring), u extrapolated
+    // through the wall velocity, u(-1) = 2 u_bot - u(0), u(nz) = 2 u_top - u(nz-1).
     auto fene = [&](int q, auto half) {
       constexpr int base = decltype(half)::value * 3;
       const int n = q * nxy + own;
-      const int slu = q & 1, slc = (q + 3) % 3;
-      const T u0 = uown[1][0], u1 = uown[1][1], u2 = uown[1][2];
+      const int su = (q + 3) % 3, sum_ = (q + 2) % 3, sup = (q + 4) % 3;
+      const int sc = q & 3, scm = (q + 3) & 3, scp = (q + 1) & 3;
+      const T u0 = L.u[su][0][lc], u1 = L.u[su][1][lc], u2 = L.u[su][2][lc];
       T um[3], up[3];
       if (q == 0) { um[0] = T(2) * (-uw) - u0; um[1] = -u1; um[2] = -u2; }
-      else { um[0] = uown[0][0]; um[1] = uown[0][1]; um[2] = uown[0][2]; }
+      else { um[0] = L.u[sum_][0][lc]; um[1] = L.u[sum_][1][lc]; um[2] = L.u[sum_][2][lc]; }
       if (q == nz - 1) { up[0] = T(2) * uw - u0; up[1] = -u1; up[2] = -u2; }
-      else { up[0] = uown[2][0]; up[1] = uown[2][1]; up[2] = uown[2][2]; }
+      else { up[0] = L.u[sup][0][lc]; up[1] = L.u[sup][1][lc]; up[2] = L.u[sup][2][lc]; }
       T Gm[3][3];
 #pragma unroll
       for (int bb = 0; bb < 3; ++bb) {
-        Gm[0][bb] = T(0.5) * (L.u[slu][bb][lc + 1] - L.u[slu][bb][lc - 1]);
-        Gm[1][bb] = T(0.5) * (L.u[slu][bb][lc + HX1] - L.u[slu][bb][lc - HX1]);
+        Gm[0][bb] = T(0.5) * (L.u[su][bb][lc + 1] - L.u[su][bb][lc - 1]);
+        Gm[1][bb] = T(0.5) * (L.u[su][bb][lc + HX1] - L.u[su][bb][lc - HX1]);
         Gm[2][bb] = T(0.5) * (up[bb] - um[bb]);
       }
       T c[6];
 #pragma unroll
-      for (int i = 0; i < 6; ++i) c[i] = Cown[2][i];
+      for (int i = 0; i < 6; ++i) c[i] = L.C[sc][i][lc];
       const double tr = (double)c[0] + (double)c[1] + (double)c[2];
       if (base == 0 && tr >= L2) st |= ST_FENE;
       const T fP = (T)((L2 - 3.0) / (L2 - tr));
@@ -532,9 +365,9 @@ k_step(StepArgs<T, S> a) {
         const int k = base + kk;
         const T ck = c[k];
         T adv = 0;
-        adv += ua0 * (ck - L.C[slc][kk][lc - 1]) + ub0 * (L.C[slc][kk][lc + 1] - ck);
-        adv += ua1 * (ck - L.C[slc][kk][lc - HX1]) + ub1 * (L.C[slc][kk][lc + HX1] - ck);
-        adv += ua2 * (ck - Cown[3][k]) + ub2 * (Cown[1][k] - ck);
+        adv += ua0 * (ck - L.C[sc][k][lc - 1]) + ub0 * (L.C[sc][k][lc + 1] - ck);
+        adv += ua1 * (ck - L.C[sc][k][lc - HX1]) + ub1 * (L.C[sc][k][lc + HX1] - ck);
+        adv += ua2 * (ck - L.C[scm][k][lc]) + ub2 * (L.C[scp][k][lc] - ck);
         T Sk = 0;
 #pragma unroll
         for (int mm = 0; mm < 3; ++mm)
@@ -547,35 +380,152 @@ k_step(StepArgs<T, S> a) {
       if (!isfinite(csum)) st |= ST_NAN;
     };
 
+    // ---- phase Y: stage C of plane r; stress-divergence terms of plane r ------
+    auto stage_c_and_divergence = [&](int r) {
+      if (!visc) return;
+      const int sl4 = r & 3;
+#pragma unroll
+      for (int k = 0; k < K2; ++k) {
+        if (q1[k] >= 0) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) L.C[sl4][c][q1[k]] = cst[k][c];
+        }
+      }
+      // F^P_a = sum_b [T_ab(x+e_b) - T_ab(x-e_b)]/2: the x and y terms from
+      // plane r; T_az(r) enters the node above with + and the node below
+      // with -
+      const int c2 = c2of1;
+      const T dx0 = T(0.5) * (L.stress[0][c2 + 1] - L.stress[0][c2 - 1]);
+      const T dx1 = T(0.5) * (L.stress[3][c2 + 1] - L.stress[3][c2 - 1]);
+      const T dx2 = T(0.5) * (L.stress[4][c2 + 1] - L.stress[4][c2 - 1]);
+      const T dy0 = T(0.5) * (L.stress[3][c2 + HX2] - L.stress[3][c2 - HX2]);
+      const T dy1 = T(0.5) * (L.stress[1][c2 + HX2] - L.stress[1][c2 - HX2]);
+      const T dy2 = T(0.5) * (L.stress[5][c2 + HX2] - L.stress[5][c2 - HX2]);
+      acc[1][0] += dx0 + dy0;
+      acc[1][1] += dx1 + dy1;
+      acc[1][2] += dx2 + dy2;
+      const T z0h = T(0.5) * L.stress[4][c2], z1h = T(0.5) * L.stress[5][c2];
+      const T z2h = T(0.5) * L.stress[2][c2];
+      acc[0][0] += z0h; acc[0][1] += z1h; acc[0][2] += z2h;
+      acc[2][0] -= z0h; acc[2][1] -= z1h; acc[2][2] -= z2h;
+    };
+
+    // ---- phase Y: plane m = r-1 of the 1-frame: forces, velocity shift,
+    // records, moments, u
+    auto finalise = [&](int m) {
+      const int sm = (m + 3) % 3, smm = (m + 2) % 3, smp = (m + 4) % 3;
+      const int c2 = c2of1;
+      const T rA = L.rho[sm][0][c2], rB = L.rho[sm][1][c2];
+      // Shan-Chen: F_A = -G rho_A sum_i 3 w_i rho_B(x+c_i) c_i (and A<->B)
+      T sA[3] = {T(0), T(0), T(0)}, sB[3] = {T(0), T(0), T(0)};
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const int sl = CZ[i] == 0 ? sm : (CZ[i] > 0 ? smp : smm);
+        const int nb = c2 + CY[i] * HX2 + CX[i];
+        const T nA = L.rho[sl][0][nb], nB = L.rho[sl][1][nb];
+        const T wt = T(3) * wgt<T>(i);
+        if (CX[i] != 0) { sA[0] += (wt * T(CX[i])) * nB; sB[0] += (wt * T(CX[i])) * nA; }
+        if (CY[i] != 0) { sA[1] += (wt * T(CY[i])) * nB; sB[1] += (wt * T(CY[i])) * nA; }
+        if (CZ[i] != 0) { sA[2] += (wt * T(CZ[i])) * nB; sB[2] += (wt * T(CZ[i])) * nA; }
+      }
+      T FA[3], FB[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        FA[c] = -G * rA * sA[c];
+        FB[c] = -G * rB * sB[c];
+      }
+      const T irt = T(1) / (rA + rB);
+      if (visc) {
+        // polymer force split over the components by mass fraction
+        const T fa = rA * irt, fb = rB * irt;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          FA[c] = FA[c] + fa * acc[0][c];
+          FB[c] = FB[c] + fb * acc[0][c];
+        }
+      }
+      // velocity shift u' = sum(j_s/tau_s)/sum(rho_s/tau_s),
+      // u^eq_s = u' + tau_s F_s/rho_s
+      const T iden = T(1) / (rA * itA + rB * itB);
+      const T qA = tA / rA, qB = tB / rB;
+      T ueA[3], ueB[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T up = (jv[c] * itA + jv[3 + c] * itB) * iden;
+        ueA[c] = up + qA * FA[c];
+        ueB[c] = up + qB * FB[c];
+      }
+      if (has1) {
+#pragma unroll
+        for (int cp = 0; cp < 2; ++cp) {
+          const T rs = cp ? rB : rA;
+          const T* ue = cp ? ueB : ueA;
+          const T w = cp ? itB : itA;
+          const T wr = w * rs, w1 = T(1) - w;
+          const T usq = ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2];
+          V4<T> r0, r1;
+          r0.x = rs - T(1.5) * wr * usq;
+          r0.y = wr * ue[0] + w1 * jv[3 * cp];
+          r0.z = wr * ue[1] + w1 * jv[3 * cp + 1];
+          r0.w = wr * ue[2] + w1 * jv[3 * cp + 2];
+          r1.x = ue[0]; r1.y = ue[1]; r1.z = ue[2];
+          r1.w = T(4.5) * wr;
+          L.rec[sm][cp][0][e1] = r0;
+          L.rec[sm][cp][1][e1] = r1;
+        }
+        if (inner) {
+          const int s2 = m & 1;
+          L.M[s2][0][0][mcol] = rA;
+          L.M[s2][1][0][mcol] = rB;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            L.M[s2][0][1 + c][mcol] = jv[c];
+            L.M[s2][1][1 + c][mcol] = jv[3 + c];
+          }
+        }
+        if (visc) {
+          // physical velocity u = (j_A + j_B + (F_A + F_B)/2)/rho
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            L.u[sm][c][e1] = (jv[c] + jv[3 + c] + T(0.5) * (FA[c] + FB[c])) * irt;
+        }
+      }
+    };
+    auto shift_acc = [&]() {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        acc[0][c] = acc[1][c];
+        acc[1][c] = acc[2][c];
+        acc[2][c] = T(0);
+      }
+    };
+
     const int z0 = tl.z0, zend = min(tl.z0 + a.bz, nz);
-    auto iter = [&](int r, Buf& use, Buf& load) {
-      __syncthreads();   // (A0) the previous plane's readers are done
+    load_raw(z0 - 2);
+    load_j(z0 - 3);
+    load_pops(clampz(z0 - 4, nz));
+    for (int r = z0 - 2; r <= zend + 2; ++r) {
+      __syncthreads();   // (1) readers of the previous iteration are done
       ingest(r);
-      // (B) loads for the next iterations; past the lattice or the tile they
+      // loads for the next iterations; past the lattice or the tile they
       // re-read clamped planes (in bounds, unused), so every load issues
-      // unconditionally and in this order
+      // unconditionally
       load_raw(r + 1);
-      load_j(r, load.j);
-      load_pops(clampz(r - 1, nz), load.f);
-      __syncthreads();   // (C) plane r staged
-      accumulate();
-      const int m = r - 1;
-      finalise(m, m >= z0 - 1 && m <= zend && m >= 0 && m < nz, use.j);
-      __syncthreads();   // (F) records of plane r-1 staged
-      const int q = r - 2;
+      const int q = r - 3;
       if (q >= z0 && q < zend && active) {
-        collide(q, use.f);
+        collide(q);
         if (visc) {
           if (s) fene(q, std::integral_constant<int, 1>{});
           else fene(q, std::integral_constant<int, 0>{});
         }
       }
-    };
-    Buf b0, b1;
-    load_raw(z0 - 2);
-    for (int r = z0 - 2; r <= zend + 1; r += 2) {
-      iter(r, b0, b1);
-      if (r + 1 <= zend + 1) iter(r + 1, b1, b0);
+      load_pops(clampz(r - 2, nz));
+      __syncthreads();   // (2) plane r staged, plane r-3 collided
+      stage_c_and_divergence(r);
+      const int m = r - 1;
+      if (m >= z0 - 1 && m <= zend && m >= 0 && m < nz) finalise(m);
+      shift_acc();
+      load_j(r);
     }
     if (st) atomicOr(a.P.status + tl.run, st);
   }
@@ -668,7 +618,7 @@ bool step_shape_ok(int bx, int by, bool fp64) {
 
 template <typename T, typename S, int BX, int BY>
 void launch_step_shape(const StepArgs<T, S>& a, dim3 grid, hipStream_t st) {
-  if constexpr (step_fits<BX, BY, T>()) k_step<T, S, BX, BY><<<grid, dim3(BX, BY), 0, st>>>(a);
+  if constexpr (step_fits<BX, BY, T>()) k_step<T, S, BX, BY><<<grid, dim3(BX, BY, 2), 0, st>>>(a);
 }
 
 template <typename T, typename S>

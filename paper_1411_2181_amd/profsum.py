@@ -1,4 +1,4 @@
-"""Summaries of rocprofv3 output for the step kernels.
+"""Summaries of rocprofv3 output for the step kernel.
 
     python -m paper_1411_2181_amd.profsum trace KERNEL_TRACE.csv [--box 512,256,128]
     python -m paper_1411_2181_amd.profsum traffic FETCH.csv WRITE.csv --precision fp32 \
@@ -6,8 +6,9 @@
     python -m paper_1411_2181_amd.profsum sq SQ_COUNTERS.csv [--box 512,256,128]
 
 ``trace`` groups the dispatches of a ``--kernel-trace`` run by kernel and
-launch shape (bx x by x bz, recovered from the grid size and the box) and
-prints their mean durations as a Markdown table.
+launch shape (bx x by x bz, recovered from the grid size and the box: one
+workgroup of 2 bx by threads per tile) and prints their mean durations as a
+Markdown table.
 
 ``traffic`` turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of
 ``bench.py --pmc-pass`` into HBM bytes per dispatch.  Each counter is scaled
@@ -30,14 +31,12 @@ from collections import defaultdict
 from .build import source_hash
 
 COPY_BYTES = 1 << 30
-_STEP = re.compile(r"lbm::k_(force|collide|fene)<[^,]+, [^,]+, (\d+), (\d+)>")
+_STEP = re.compile(r"lbm::k_(step)<[^,]+, [^,]+, (\d+), (\d+)>")
 
 
 def _launch(kind, bx, by, grid_items, wg_items, box):
     nx, ny, nz = box
     wg = grid_items // wg_items
-    if kind == "collide":
-        wg //= 2                      # one workgroup per component
     cols = -(-nx // bx) * -(-ny // by)
     bz = nz * cols // wg if wg else 0
     return f"{bx}x{by}x{bz}"
@@ -116,8 +115,7 @@ def traffic_table(fetch_csv, write_csv, box):
             f, w = statistics.mean(v["fetch"]), statistics.mean(v["write"])
             ent[k] = dict(fetch=round(f), write=round(w), bytes=round(f + w),
                           bytes_per_node=round((f + w) / nodes, 2), us=round(statistics.mean(v["us"]), 1))
-        if len(ent) == 3:
-            ent["step_bytes_per_node"] = round(sum(e["bytes"] for e in ent.values()) / nodes, 2)
+        if "k_step" in ent:
             table[key] = ent
     return table, scale
 
@@ -190,12 +188,13 @@ def main(argv=None):
         return 0
     table, scale = traffic_table(a.fetch_csv, a.write_csv, box)
     print(f"copy-reference scale factors: FETCH_SIZE x{scale['fetch']:.4f}, WRITE_SIZE x{scale['write']:.4f}")
-    print("| launch | k_force B/node | k_collide B/node | k_fene B/node | step B/node |")
+    print("| launch | fetch B/node | write B/node | step B/node | mean us |")
     print("|---|---|---|---|---|")
-    for key in sorted(table, key=lambda k: table[k]["step_bytes_per_node"]):
-        e = table[key]
-        print(f"| {key} | {e['k_force']['bytes_per_node']} | {e['k_collide']['bytes_per_node']} | "
-              f"{e['k_fene']['bytes_per_node']} | {e['step_bytes_per_node']} |")
+    nodes = box[0] * box[1] * box[2]
+    for key in sorted(table, key=lambda k: table[k]["k_step"]["bytes_per_node"]):
+        e = table[key]["k_step"]
+        print(f"| {key} | {e['fetch'] / nodes:.1f} | {e['write'] / nodes:.1f} | "
+              f"{e['bytes_per_node']} | {e['us']} |")
     if a.json:
         data = {}
         if os.path.exists(a.json):

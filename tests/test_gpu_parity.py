@@ -123,9 +123,9 @@ def test_small_droplet_2000_steps_parity(lbm, oracle_2000, case):
 def test_launch_shapes_bit_identical(lbm):
     d = WL.small_droplet_viscoelastic()
     ref = None
-    for shape in [dict(bx=32, by=8, bz=1), dict(bx=64, by=4, bz=3),
-                  dict(bx=16, by=16, bz=8, persistent=64), dict(bx=32, by=8, bz=32),
-                  dict(bx=64, by=4, bz=5, persistent=16)]:
+    for shape in [dict(bx=16, by=8, bz=1), dict(bx=8, by=16, bz=3),
+                  dict(bx=16, by=8, bz=8, persistent=64), dict(bx=8, by=16, bz=32),
+                  dict(bx=16, by=8, bz=5, persistent=8)]:
         s = lbm.Solver(d, "fp64")
         s.set_launch(**shape)
         s.step(25)
@@ -339,6 +339,10 @@ def _column_block(a, x, y, nx, ny, h=4):
     return np.ascontiguousarray(a[..., yi, :][..., xi])
 
 
+FULL_LAUNCH = {"fp64": dict(bx=16, by=8, bz=64, persistent=2048),
+               "fp32": dict(bx=32, by=8, bz=128, persistent=0)}
+
+
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
 def test_full_size_one_step_sampled(lbm, precision, tol):
@@ -348,9 +352,9 @@ def test_full_size_one_step_sampled(lbm, precision, tol):
     import bench
     p, _ = bench.workload_params()
     nx, ny, nz = p["nx"], p["ny"], p["nz"]
-    print(f"case full size {nx}x{ny}x{nz} {precision}, launch 32x8x64 persistent 2048", flush=True)
+    print(f"case full size {nx}x{ny}x{nz} {precision}, launch {FULL_LAUNCH[precision]}", flush=True)
     s = lbm.Solver(p, precision)
-    s.set_launch(bx=32, by=8, bz=64, persistent=2048)
+    s.set_launch(**FULL_LAUNCH[precision])
     s.step(100)
     f0, C0 = s.export("f"), s.export("C")
     s.step(1)

@@ -63,26 +63,23 @@ def test_traffic_table_scaling_and_launch_decoding(tmp_path):
     from paper_1411_2181_amd import profsum
     box = (64, 32, 16)                     # 32x8 tiles, bz = 8: 2 x 4 columns x 2 z blocks
     nodes = 64 * 32 * 16
-    wg, items = 16, 256
-    name = "void lbm::k_{}<float, float, 32, 8>(lbm::StepArgs<float, float>)"
+    wg, items = 16, 512                    # one workgroup of 2 bx by threads per tile
+    name = "void lbm::k_step<float, float, 32, 8>(lbm::StepArgs<float, float>)"
     copy = "void at::native::copy_kernel(float)"
     # counters in KiB: the copy reads 1 GiB and writes 1 GiB; FETCH_SIZE reports half
     fetch = [[copy, 1 << 28, 256, "FETCH_SIZE", (1 << 20) / 2, 0, 1000],
-             [name.format("force"), wg * items, items, "FETCH_SIZE", 50.0, 0, 2000],
-             [name.format("collide"), 2 * wg * items, items, "FETCH_SIZE", 100.0, 0, 5000],
-             [name.format("fene"), wg * items, items, "FETCH_SIZE", 20.0, 0, 1000]]
+             [name, wg * items, items, "FETCH_SIZE", 100.0, 0, 5000],
+             [name, wg * items, items, "FETCH_SIZE", 120.0, 0, 7000]]
     write = [[copy, 1 << 28, 256, "WRITE_SIZE", 1 << 20, 0, 1000],
-             [name.format("force"), wg * items, items, "WRITE_SIZE", 30.0, 0, 2000],
-             [name.format("collide"), 2 * wg * items, items, "WRITE_SIZE", 200.0, 0, 5000],
-             [name.format("fene"), wg * items, items, "WRITE_SIZE", 10.0, 0, 1000]]
+             [name, wg * items, items, "WRITE_SIZE", 200.0, 0, 5000],
+             [name, wg * items, items, "WRITE_SIZE", 200.0, 0, 5000]]
     _counter_csv(tmp_path / "f.csv", fetch)
     _counter_csv(tmp_path / "w.csv", write)
     table, scale = profsum.traffic_table(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), box)
     assert scale["fetch"] == pytest.approx(2.0) and scale["write"] == pytest.approx(1.0)
     (key,) = table
     assert key == "32x8x8"
-    e = table[key]
-    assert e["k_collide"]["fetch"] == round(100.0 * 1024 * 2) and e["k_collide"]["write"] == 200 * 1024
-    want = (50 * 2 + 30 + 100 * 2 + 200 + 20 * 2 + 10) * 1024 / nodes
-    assert e["step_bytes_per_node"] == pytest.approx(want, abs=0.01)
-    assert e["k_force"]["us"] == pytest.approx(2.0)
+    e = table[key]["k_step"]
+    assert e["fetch"] == round(110.0 * 1024 * 2) and e["write"] == 200 * 1024
+    assert e["bytes_per_node"] == pytest.approx((220 + 200) * 1024 / nodes, abs=0.01)
+    assert e["us"] == pytest.approx(5.5)
