@@ -201,8 +201,12 @@ int validate(const lbm_params* p) {
   const int64_t n = (int64_t)p->nx * p->ny * p->nz;
   if (n >= (int64_t)1 << 31) return LBM_EINVAL;
   if (p->precision < LBM_FP64 || p->precision > LBM_FP16S) return LBM_EINVAL;
-  // one population array of a run is addressed with 32-bit byte offsets
+  // every per-run array (populations, densities, momenta, C) is addressed
+  // with 32-bit byte offsets
   if (n * (int64_t)elem_S(p->precision) >= (int64_t)1 << 32) return LBM_EINVAL;
+  if (n * (int64_t)elem_T(p->precision) >= (int64_t)1 << 32) return LBM_EINVAL;
+  // the 19 direction arrays of one component are addressed from one base
+  if (19 * ld_of(n) * (int64_t)elem_S(p->precision) >= (int64_t)1 << 32) return LBM_EINVAL;
   if (!(std::fabs(p->u_wall) < 0.2)) return LBM_EINVAL;
   if (!(p->radius >= 0.0) || !(p->radius < 0.5 * p->nz)) return LBM_EINVAL;
   if (!(p->rho_major > 0.0) || !(p->rho_minor > 0.0)) return LBM_EINVAL;

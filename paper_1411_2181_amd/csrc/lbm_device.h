@@ -7,6 +7,8 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbm {
 
 // ---- D3Q19 (direction order documented in include/lbmve.h) -------------
@@ -157,6 +159,21 @@ struct Pools {
 constexpr uint32_t ST_NAN = 1u;
 constexpr uint32_t ST_FENE = 2u;
 constexpr uint32_t ST_CC = 4u;   // component labelling hit its iteration cap
+
+// Element of a uniform array base at a 32-bit byte offset: global accesses
+// then take the scalar base + 32-bit vector offset form (the library keeps
+// every per-run array below 4 GiB).
+template <typename P>
+__device__ __forceinline__ P* boff(P* base, uint32_t off) {
+  using B = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  return reinterpret_cast<P*>(reinterpret_cast<B*>(base) + off);
+}
+
+// Reciprocal in the compute type: FP64 divides exactly; FP32 uses the
+// hardware reciprocal (1 ulp), whose error is far below the FP32 path's
+// bars against FP64.
+__device__ __forceinline__ double rcpT(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcpT(float x) { return __builtin_amdgcn_rcpf(x); }
 
 __device__ __forceinline__ int wrapm(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 __device__ __forceinline__ int clampz(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }

@@ -97,7 +97,12 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
   using St = Store<T, S>;
   const T kS = T(St::kScale), ikS = T(1.0 / St::kScale);
   const int g = *a.gstep;
-  const int tx = (int)threadIdx.x, ty = (int)threadIdx.y, s = (int)threadIdx.z;
+  // every wave lies in one threadIdx.z half (bx * by is a multiple of 64),
+  // so the component index is wave-uniform: read it as a scalar, which keeps
+  // the per-component array bases in scalar registers
+  static_assert((BX * BY) % 64 == 0, "a wave must not straddle the two components");
+  const int tx = (int)threadIdx.x, ty = (int)threadIdx.y;
+  const int s = __builtin_amdgcn_readfirstlane((int)threadIdx.z);
   const int tid = (s * BY + ty) * BX + tx;
 
   // this thread's 1-frame position (threads past N1 repeat the last one and
@@ -144,6 +149,7 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
     const T chi_lo = T(R.chi_lo), ichr = T(R.inv_chi_range), eP = T(R.etaP_over_tauP);
     const T itP = T(R.inv_tauP);
     const double L2 = R.L2;
+    const T L2m3 = T(R.L2 - 3.0);
     const uint32_t hstep = ((uint32_t)(R.base + g) * 2u + (uint32_t)s) * 0x85ebca77u;
 
     const T* __restrict__ rho_in = a.P.rho[par] + 2 * R.off;
@@ -173,9 +179,9 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
     const uint32_t rowb[3] = {(uint32_t)(ym * nx) * SZ, (uint32_t)(yq * nx) * SZ,
                               (uint32_t)(yp * nx) * SZ};
     const uint32_t colb[3] = {(uint32_t)xm * SZ, (uint32_t)xq * SZ, (uint32_t)xp * SZ};
-    auto arr = [&](const S* base, int i, uint32_t off) {
-      return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base + (int64_t)i * N) + off);
-    };
+    // byte offset of direction i's array from the component's first array
+    // (a component's 19 arrays span < 4 GiB, which the library checks)
+    const uint32_t db = (uint32_t)N * SZ;
     const int own = yq * nx + xq;
 
     T raw[K2][8];    // densities and C of the 2-frame positions (next plane)
@@ -190,23 +196,24 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
     uint32_t st = 0;
 
     // ---- loads ---------------------------------------------------------------
+    constexpr uint32_t TB = sizeof(T);
     auto load_raw = [&](int r) {
-      const int zo = clampz(r, nz) * nxy;
+      const uint32_t zo = (uint32_t)(clampz(r, nz) * nxy) * TB;
 #pragma unroll
       for (int k = 0; k < K2; ++k) {
-        const int m = zo + col2[k];
-        raw[k][0] = rho_in[m];
-        raw[k][1] = rho_in[N + m];
+        const uint32_t mo = zo + (uint32_t)col2[k] * TB;
+        raw[k][0] = *boff(rho_in, mo);
+        raw[k][1] = *boff(rho_in + N, mo);
         if (visc) {
 #pragma unroll
-          for (int c = 0; c < 6; ++c) raw[k][2 + c] = C_in[c * N + m];
+          for (int c = 0; c < 6; ++c) raw[k][2 + c] = *boff(C_in + c * N, mo);
         }
       }
     };
     auto load_j = [&](int r) {
-      const int m = clampz(r, nz) * nxy + col1;
+      const uint32_t mo = (uint32_t)(clampz(r, nz) * nxy + col1) * TB;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) jv[c] = J_in[c * N + m];
+      for (int c = 0; c < 6; ++c) jv[c] = *boff(J_in + c * N, mo);
     };
     // populations arriving at the own column in plane zz: pulled from
     // x - c_i, or the node's own opposite population where the link crosses
@@ -218,10 +225,10 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
         const int zs = zz - CZ[i];
         const uint32_t off = (uint32_t)zs * pb + rowb[1 - CY[i]] + colb[1 - CX[i]];
         if (CZ[i] == 0) {
-          pops[i] = St::load(arr(fs, i, off), 0);
+          pops[i] = St::load(boff(fs, (uint32_t)i * db + off), 0);
         } else {
           const bool in = zs >= 0 && zs < nz;
-          pops[i] = St::load(arr(fs, in ? i : OPPI[i], in ? off : ownb), 0);
+          pops[i] = St::load(boff(fs, (uint32_t)(in ? i : OPPI[i]) * db + (in ? off : ownb)), 0);
         }
       }
     };
@@ -240,10 +247,11 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
           // T = chi (eta_P/tau_P)(f C - I): chi the clamped rescaled mass
           // fraction of the polymer phase's component, f in FP64
           const T rp = vph == 0 ? rA : rB;
-          T chi = (rp / (rA + rB) - chi_lo) * ichr;
+          T chi = (rp * rcpT(rA + rB) - chi_lo) * ichr;
           chi = chi < T(0) ? T(0) : (chi > T(1) ? T(1) : chi);
+          // L^2 - tr C in FP64 (the cancellation as tr C -> L^2)
           const double tr = (double)raw[k][2] + (double)raw[k][3] + (double)raw[k][4];
-          const T fP = (T)((L2 - 3.0) / (L2 - tr));
+          const T fP = L2m3 * rcpT(T(L2 - tr));
           const T coef = chi * eP;
           if (has2[k]) {
 #pragma unroll
@@ -314,13 +322,13 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
         if (CY[i] != 0) cd += T(CY[i]) * dj1;
         if (CZ[i] != 0) cd += T(CZ[i]) * dj2;
         const T out = pops[i] - wgt<T>(i) * (drho + T(3) * cd);
-        S* dst = reinterpret_cast<S*>(reinterpret_cast<char*>(fo + (int64_t)i * N) + nb);
-        St::put(dst, 0, out, hb + (uint32_t)i * 0x9e3779b9u);
+        St::put(boff(fo, (uint32_t)i * db + nb), 0, out, hb + (uint32_t)i * 0x9e3779b9u);
       }
-      rho_out[n] = rnew;
-      j_out[n] = jn0;
-      j_out[N + n] = jn1;
-      j_out[2 * N + n] = jn2;
+      const uint32_t no = (uint32_t)n * TB;
+      *boff(rho_out, no) = rnew;
+      *boff(j_out, no) = jn0;
+      *boff(j_out + N, no) = jn1;
+      *boff(j_out + 2 * N, no) = jn2;
       if (!isfinite(rnew + jn0 + jn1 + jn2)) st |= ST_NAN;
     };
 
@@ -352,7 +360,7 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
       for (int i = 0; i < 6; ++i) c[i] = L.C[sc][i][lc];
       const double tr = (double)c[0] + (double)c[1] + (double)c[2];
       if (base == 0 && tr >= L2) st |= ST_FENE;
-      const T fP = (T)((L2 - 3.0) / (L2 - tr));
+      const T fP = L2m3 * rcpT(T(L2 - tr));
       const T ua0 = u0 > T(0) ? u0 : T(0), ub0 = u0 < T(0) ? u0 : T(0);
       const T ua1 = u1 > T(0) ? u1 : T(0), ub1 = u1 < T(0) ? u1 : T(0);
       const T ua2 = u2 > T(0) ? u2 : T(0), ub2 = u2 < T(0) ? u2 : T(0);
@@ -374,7 +382,7 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
           Sk += c[SYM[KK[k]][mm]] * Gm[mm][LL[k]] + Gm[mm][KK[k]] * c[SYM[mm][LL[k]]];
         const T delta = k < 3 ? T(1) : T(0);
         const T cn = ck + (-adv + Sk - (fP * ck - delta) * itP);
-        C_out[k * N + n] = cn;
+        *boff(C_out + k * N, (uint32_t)n * TB) = cn;
         csum += cn;
       }
       if (!isfinite(csum)) st |= ST_NAN;
@@ -434,7 +442,7 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
         FA[c] = -G * rA * sA[c];
         FB[c] = -G * rB * sB[c];
       }
-      const T irt = T(1) / (rA + rB);
+      const T irt = rcpT(rA + rB);
       if (visc) {
         // polymer force split over the components by mass fraction
         const T fa = rA * irt, fb = rB * irt;
@@ -446,8 +454,8 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
       }
       // velocity shift u' = sum(j_s/tau_s)/sum(rho_s/tau_s),
       // u^eq_s = u' + tau_s F_s/rho_s
-      const T iden = T(1) / (rA * itA + rB * itB);
-      const T qA = tA / rA, qB = tB / rB;
+      const T iden = rcpT(rA * itA + rB * itB);
+      const T qA = tA * rcpT(rA), qB = tB * rcpT(rB);
       T ueA[3], ueB[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
