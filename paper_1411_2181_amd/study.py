@@ -32,10 +32,10 @@ Searches: tolerance 0.02 (Ca_cr located within +-0.01), window
 window; the surrogate's search starts from the network's bracket (centred
 where its break-up probability crosses 1/2, at least +-0.02 wide) and falls
 back outward when a bracket end fails (sweep.bisect).  Both advance every query's runs of a round
-as one batch (FP32 or FP16S storage).  A run lasts T_END steps; with
-``--extend-to`` a droplet still stretching at T_END runs on (sweep.simulate),
-which keeps slow binary break-ups just below the onset of ternary break-up
-from being taken as stable.  The plain FP64 one-run-at-a-time variant is timed on
+as one batch (FP32 or FP16S storage).  A run lasts T_END steps; a droplet still
+stretching at T_END runs on, check by check, up to ``--extend-to`` steps
+(default 2 T_END; sweep.simulate), which keeps slow binary break-ups just
+below the onset of ternary break-up from being taken as stable.  The plain FP64 one-run-at-a-time variant is timed on
 ``--fp64-queries`` triples.
 """
 from __future__ import annotations
@@ -429,8 +429,9 @@ def main(argv=None):
     s.add_argument("--fp64-queries", type=int, default=1)
     s.add_argument("--precision", default="fp32", choices=["fp32", "fp16s"],
                    help="storage of the batched searches")
-    s.add_argument("--extend-to", type=int, default=0,
-                   help="run a droplet still elongating at the horizon on, up to this step")
+    s.add_argument("--extend-to", type=int, default=2 * T_END,
+                   help="run a droplet still elongating at the horizon on, up to this step "
+                        "(0: fixed horizon)")
     s.add_argument("--only", default="", help="comma-separated indices of the query triples")
     s.add_argument("--plain-only", action="store_true", help="skip the surrogate's search")
     e = sub.add_parser("elongation")

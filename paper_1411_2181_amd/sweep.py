@@ -181,6 +181,7 @@ class Search:
     L2: float = 100.0
     fraction: float = 0.4
     lo_ok: bool = False      # lo verified (or assumed) stable
+    lo_assumed: bool = False # lo is the window's bottom, taken as stable without a run
     hi_ok: bool = False      # hi verified broken
     speculate: bool = True   # run the midpoint alongside unverified ends
     runs: int = 0
@@ -216,7 +217,9 @@ def bisect(searches, tol: float = 0.02, run=None, max_rounds: int = 12):
     simulated together with the midpoint (speculatively: the midpoint result
     is discarded when an end check fails; a search with speculate=False runs
     only its unverified ends until both hold).  A lower end at hard_lo is taken as
-    stable without a run (the bottom of the search window).  A failed end
+    stable without a run (the bottom of the search window) while the search
+    narrows; if the final bracket still rests on it, hard_lo is run once to
+    verify it, and a break there ends the search as "below".  A failed end
     check moves the bracket outward by twice its width, clipped to the hard
     window: lo broken -> [lo - 2w, lo] (lo now a verified broken end);
     hi stable -> [hi, hi + 2w].  A run with a non-zero status ends its search
@@ -229,14 +232,17 @@ def bisect(searches, tol: float = 0.02, run=None, max_rounds: int = 12):
         s.lo = max(s.lo, s.hard_lo)
         s.hi = min(s.hi, s.hard_hi)
         if s.lo <= s.hard_lo + 1e-12:
-            s.lo, s.lo_ok = s.hard_lo, True
+            s.lo, s.lo_ok, s.lo_assumed = s.hard_lo, True, True
     while rounds < max_rounds:
         todo, specs = [], []
         for s in searches:
             if s.done:
                 continue
             if s.lo_ok and s.hi_ok and s.hi - s.lo <= tol:
-                s.done = True
+                if s.lo_assumed:
+                    todo.append((s, "lo", s.lo))     # verify the window's bottom once
+                else:
+                    s.done = True
                 continue
             if not s.lo_ok:
                 todo.append((s, "lo", s.lo))
@@ -265,6 +271,7 @@ def bisect(searches, tol: float = 0.02, run=None, max_rounds: int = 12):
             moved = False
             if "lo" in res:
                 ca, broken, _ = res["lo"]
+                s.lo_assumed = False
                 if not broken:
                     s.lo_ok = True
                 elif ca <= s.hard_lo + 1e-12:
@@ -285,7 +292,7 @@ def bisect(searches, tol: float = 0.02, run=None, max_rounds: int = 12):
                     continue
                 else:
                     w = s.hi - s.lo
-                    s.lo, s.lo_ok = ca, True
+                    s.lo, s.lo_ok, s.lo_assumed = ca, True, False
                     s.hi, s.hi_ok = min(s.hard_hi, ca + 2.0 * w), False
                     moved = True
             if "mid" in res and not moved:
@@ -293,8 +300,8 @@ def bisect(searches, tol: float = 0.02, run=None, max_rounds: int = 12):
                 if broken:
                     s.hi, s.hi_ok = ca, True
                 else:
-                    s.lo, s.lo_ok = ca, True
+                    s.lo, s.lo_ok, s.lo_assumed = ca, True, False
         for s in searches:
-            if not s.done and s.lo_ok and s.hi_ok and s.hi - s.lo <= tol:
+            if not s.done and s.lo_ok and s.hi_ok and s.hi - s.lo <= tol and not s.lo_assumed:
                 s.done = True
     return searches, total, rounds

@@ -40,9 +40,21 @@ def test_threshold_above_and_below_the_window():
     below = search(0.10, 0.26, hard=(0.22, 0.26))                              # ca_cr ~ 0.18
     res, _, _ = sweep.bisect([above, below], tol=TOL, run=threshold_runner(calls))
     assert res[0].outside == "above" and res[0].runs == 2      # hi check + speculative midpoint
-    # the bottom of the window is taken as stable: a threshold below it ends
-    # in the lowest bracket, every run of which broke
-    assert res[1].outside == "" and res[1].lo == 0.22 and res[1].hi - res[1].lo <= TOL * 1.000001
+    # the bottom of the window is taken as stable while the search narrows;
+    # once the final bracket rests on it, it is run, breaks, and the search
+    # reports the threshold below the window
+    assert res[1].outside == "below" and res[1].lo == 0.22
+
+
+def test_bottom_of_the_window_is_verified_when_the_bracket_rests_on_it():
+    # threshold just above the window's bottom: the bracket ends on hard_lo,
+    # which is then run once and holds
+    t = ca_cr(0.5, 0.7, 0.5)
+    calls = []
+    s = search(t - 0.005, t + 0.2, hard=(t - 0.005, t + 0.2))
+    (s,), _, _ = sweep.bisect([s], tol=TOL, run=threshold_runner(calls))
+    assert s.outside == "" and s.lo == pytest.approx(t - 0.005) and s.lo_ok and not s.lo_assumed
+    assert s.lo <= t < s.hi and s.hi - s.lo <= TOL * 1.000001
 
 
 def test_exact_proposal_needs_one_round_and_two_runs():
