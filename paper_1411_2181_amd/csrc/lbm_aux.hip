@@ -161,20 +161,27 @@ __global__ void k_obs_final(AuxArgs<T, S> a, int nblocks) {
 
 // ---- connected components of {phi > 0} -----------------------------------------
 // Lock-free union-find on node indices: each set's root is its smallest
-// index; unions link the larger root under the smaller with atomicMin.
-// Parent pointers only decrease, so every walk ends; a generous iteration
-// cap turns any unforeseen livelock into a status flag instead of a hang.
+// index; unions link the larger root under the smaller with atomicMin, so
+// parent pointers only decrease.  Root searches halve the path as they walk
+// (each visited node is pointed at its grandparent, with atomicMin: the
+// grandparent is in the same set and no larger than the parent), which keeps
+// the trees shallow even for a long, thread-shaped droplet whose unions would
+// otherwise build chains as long as the thread.  A generous iteration cap
+// turns any unforeseen livelock into a status flag instead of a hang.
 constexpr int CC_CAP = 1 << 22;
 
 __device__ __forceinline__ int32_t ld_agent(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ int32_t cc_find(const int32_t* L, int32_t i) {
-  int32_t p = ld_agent(L + i);
-  for (int guard = 0; p != i && guard < CC_CAP; ++guard) {
-    i = p;
-    p = ld_agent(L + i);
+__device__ __forceinline__ int32_t cc_find(int32_t* L, int32_t i) {
+  for (int guard = 0; guard < CC_CAP; ++guard) {
+    const int32_t p = ld_agent(L + i);
+    if (p == i) return i;
+    const int32_t gp = ld_agent(L + p);
+    if (gp == p) return p;
+    atomicMin(L + i, gp);   // path halving
+    i = gp;
   }
   return i;
 }

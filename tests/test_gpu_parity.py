@@ -463,3 +463,45 @@ def test_layered_couette_parity(lbm):
         assert rel(g[k], ref) <= 1e-10, k
     assert abs(o.C[4]).max() > 1e-2      # the polymer layer is sheared
     s.close()
+
+
+def test_component_labelling_of_a_thread_shaped_droplet(lbm):
+    """A droplet at the R = 24 study scale stretched into a long thread of
+    radius 4 that has broken in two places, with bulbous ends and a small
+    satellite (the shape just after a multiple necking, Section 3): counts
+    and piece sizes against the oracle's breadth-first search, and the cost
+    of the labelling (long threads are the worst case for the union-find)."""
+    import time
+    nx, ny, nz = 320, 48, 50
+    d = WL.base_params(nx=nx, ny=ny, nz=nz, radius=24.0, u_wall=0.0)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    yc, zc = 23.5, 24.5
+    tube = (y - yc) ** 2 + (z - zc) ** 2 < 16.0
+    m = tube & (((x >= 14) & (x <= 109)) | ((x >= 113) & (x <= 199)) | ((x >= 203) & (x <= 305)))
+    m |= (x - 14) ** 2 + (y - yc) ** 2 + (z - zc) ** 2 < 81.0         # end bulbs
+    m |= (x - 305) ** 2 + (y - yc) ** 2 + (z - zc) ** 2 < 81.0
+    m |= (x - 111) ** 2 + (y - yc - 9) ** 2 + (z - zc) ** 2 < 6.25    # satellite
+    # the last piece wraps through the periodic x seam
+    m |= tube & ((x >= 316) | (x <= 14))
+    rA = np.where(m, 1.0, 0.04)
+    rB = np.where(m, 0.04, 1.0)
+    f = np.stack([d3q19.W[:, None, None, None] * rA, d3q19.W[:, None, None, None] * rB])
+    s = lbm.Solver(d, "fp32")
+    s.import_("f", f)
+    s.observe()                                   # warm-up
+    t0 = time.perf_counter()
+    s.observe()
+    t1 = time.perf_counter()
+    o = s.observe(components=True)
+    t2 = time.perf_counter()
+    sizes = component_sizes(m)
+    min_cc = -(-int((((x - (nx - 1) / 2) ** 2 + (y - (ny - 1) / 2) ** 2
+                      + (z - (nz - 1) / 2) ** 2) < 24.0 ** 2).sum()) // 100)
+    big = sorted((v for v in sizes if v >= min_cc), reverse=True)
+    print(f"case thread {nx}x{ny}x{nz}: pieces {big} (all {sizes[:6]}), min {min_cc}; "
+          f"labelling {1e3 * ((t2 - t1) - (t1 - t0)):.2f} ms", flush=True)
+    assert o["status"] == 0
+    assert o["n_components"] == len(big) == 3
+    assert o["piece_nodes"] == big + [0] * (4 - len(big))
+    assert len(sizes) == 4 and sizes[-1] < min_cc      # the satellite is not counted
+    s.close()
