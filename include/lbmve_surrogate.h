@@ -56,6 +56,20 @@ int sg_gradient(sg_ctx* s, const float* x_dev, const float* t_dev, const float* 
  * *loss_host receives the loss before the update; synchronises. */
 int sg_train_step(sg_ctx* s, const float* x_dev, const float* t_dev, const float* m_dev, int32_t n,
                   float lr, float* loss_host);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the loss
+ * and gradient of sg_gradient, written to caller-owned float32 device buffers
+ * grad_dev[sg_param_count()] and loss_dev[1] instead of host memory.  The
+ * per-row intermediates (activations, deltas, row losses) live in a fixed
+ * device array of the library (about 2 MB on each GPU it runs on, kept until
+ * the process ends), not in the context's workspace: n must be in
+ * [1, SG_NOALLOC_MAX_ROWS] (else LBM_EINVAL).  Asynchronous on the context's
+ * stream; allocates nothing and does not synchronise.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (on different
+ * streams) race.  Results are bit-identical to sg_gradient's. */
+#define SG_NOALLOC_MAX_ROWS 1024
+int sg_gradient_noalloc(sg_ctx* s, const float* x_dev, const float* t_dev, const float* m_dev,
+                        int32_t n, float* grad_dev, float* loss_dev);
 void sg_destroy(sg_ctx* s);
 
 #ifdef __cplusplus

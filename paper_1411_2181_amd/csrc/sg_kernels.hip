@@ -11,6 +11,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -235,12 +236,47 @@ Lay layout(int bmax) {
   return L;
 }
 
+// ---- scratch of the allocation-free gradient --------------------------------------
+// Per-row activations, deltas and losses of up to SG_NOALLOC_MAX_ROWS rows in
+// one file-scope device array: every GPU the library runs on holds its own
+// copy until the process ends.  In host code the array's name is only a
+// host-side stand-in: the device address is what hipGetSymbolAddress returns
+// with that device current, resolved once per device and kept below.
+constexpr size_t SC_H = (size_t)SG_NOALLOC_MAX_ROWS * NH;   // h1, h2, dz1, dz2
+constexpr size_t SC_O = (size_t)SG_NOALLOC_MAX_ROWS * NO;   // z, d
+constexpr size_t SC_FLOATS = 4 * SC_H + 2 * SC_O + SG_NOALLOC_MAX_ROWS;
+static __device__ __align__(256) float scratch[SC_FLOATS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+float* scratch_dev[MAX_DEVICES] = {};
+
+// Device address of the scratch array on the current device (nullptr if it
+// cannot be resolved).
+float* scratch_of_current_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    scratch_dev[dev] = static_cast<float*>(p);
+  }
+  return scratch_dev[dev];
+}
+
+// Buffers of one backward pass.
+struct Bufs {
+  float *h1, *h2, *z, *d, *dz1, *dz2, *rowloss, *G, *loss;
+};
+
 }  // namespace
 
 struct sg_ctx {
   int bmax = 0;
   hipStream_t stream = nullptr;
   char* ws = nullptr;
+  float* scratch = nullptr;   // this device's scratch array (allocation-free gradient)
   Lay L{};
   int step = 0;
   template <typename P>
@@ -249,18 +285,22 @@ struct sg_ctx {
 
 namespace {
 
-int backward(sg_ctx* s, const float* x, const float* t, const float* m, int n) {
+Bufs workspace_bufs(const sg_ctx* s) {
+  return Bufs{s->at<float>(s->L.h1), s->at<float>(s->L.h2), s->at<float>(s->L.z),
+              s->at<float>(s->L.d), s->at<float>(s->L.dz1), s->at<float>(s->L.dz2),
+              s->at<float>(s->L.rowloss), s->at<float>(s->L.G), s->at<float>(s->L.loss)};
+}
+
+int backward(sg_ctx* s, const float* x, const float* t, const float* m, int n, const Bufs& b) {
   hipStream_t st = s->stream;
   const uint16_t* Wb = s->at<uint16_t>(s->L.Wb);
-  float *h1 = s->at<float>(s->L.h1), *h2 = s->at<float>(s->L.h2), *z = s->at<float>(s->L.z);
-  float *d = s->at<float>(s->L.d), *dz1 = s->at<float>(s->L.dz1), *dz2 = s->at<float>(s->L.dz2);
-  k_forward<<<(n + ROWS - 1) / ROWS, NH, 0, st>>>(x, n, Wb, z, h1, h2);
-  k_delta<<<(n + 255) / 256, 256, 0, st>>>(z, t, m, n, d, s->at<float>(s->L.rowloss));
+  k_forward<<<(n + ROWS - 1) / ROWS, NH, 0, st>>>(x, n, Wb, b.z, b.h1, b.h2);
+  k_delta<<<(n + 255) / 256, 256, 0, st>>>(b.z, t, m, n, b.d, b.rowloss);
   const int64_t nh = (int64_t)n * NH;
-  k_back2<<<(unsigned)((nh + 255) / 256), 256, 0, st>>>(d, h2, Wb, n, dz2);
-  k_back1<<<(unsigned)((nh + 255) / 256), 256, 0, st>>>(dz2, h1, Wb, n, dz1);
-  k_wgrad<<<(NP + 255) / 256, 256, 0, st>>>(x, h1, h2, d, dz1, dz2, n, s->at<float>(s->L.G));
-  k_loss<<<1, 256, 0, st>>>(s->at<float>(s->L.rowloss), n, s->at<float>(s->L.loss));
+  k_back2<<<(unsigned)((nh + 255) / 256), 256, 0, st>>>(b.d, b.h2, Wb, n, b.dz2);
+  k_back1<<<(unsigned)((nh + 255) / 256), 256, 0, st>>>(b.dz2, b.h1, Wb, n, b.dz1);
+  k_wgrad<<<(NP + 255) / 256, 256, 0, st>>>(x, b.h1, b.h2, b.d, b.dz1, b.dz2, n, b.G);
+  k_loss<<<1, 256, 0, st>>>(b.rowloss, n, b.loss);
   return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EHIP;
 }
 
@@ -287,6 +327,12 @@ int sg_init(int32_t bmax, void* ws, size_t bytes, void* stream, sg_ctx** out) {
   s->stream = (hipStream_t)stream;
   s->ws = (char*)ws;
   s->L = L;
+  // the scratch array of the device this context runs on (current now)
+  s->scratch = scratch_of_current_device();
+  if (!s->scratch) {
+    delete s;
+    return LBM_EHIP;
+  }
   *out = s;
   return LBM_OK;
 }
@@ -330,7 +376,7 @@ int sg_forward(sg_ctx* s, const float* x, int32_t n, float* z) {
 int sg_gradient(sg_ctx* s, const float* x, const float* t, const float* m, int32_t n, float* grad,
                 float* loss) {
   if (!s || !x || !t || !m || !grad || !loss || n < 1 || n > s->bmax) return LBM_EINVAL;
-  const int e = backward(s, x, t, m, n);
+  const int e = backward(s, x, t, m, n, workspace_bufs(s));
   if (e) return e;
   if (hipMemcpyAsync(grad, s->at<float>(s->L.G), NP * 4, hipMemcpyDeviceToHost, s->stream) ||
       hipMemcpyAsync(loss, s->at<float>(s->L.loss), 4, hipMemcpyDeviceToHost, s->stream) ||
@@ -342,7 +388,7 @@ int sg_gradient(sg_ctx* s, const float* x, const float* t, const float* m, int32
 int sg_train_step(sg_ctx* s, const float* x, const float* t, const float* m, int32_t n, float lr,
                   float* loss) {
   if (!s || !x || !t || !m || !loss || n < 1 || n > s->bmax || !(lr > 0.f)) return LBM_EINVAL;
-  int e = backward(s, x, t, m, n);
+  int e = backward(s, x, t, m, n, workspace_bufs(s));
   if (e) return e;
   s->step += 1;
   const float bc1 = 1.f - powf(0.9f, (float)s->step);
@@ -355,6 +401,17 @@ int sg_train_step(sg_ctx* s, const float* x, const float* t, const float* m, int
       hipStreamSynchronize(s->stream))
     return LBM_EHIP;
   return LBM_OK;
+}
+
+int sg_gradient_noalloc(sg_ctx* s, const float* x, const float* t, const float* m, int32_t n,
+                        float* grad_dev, float* loss_dev) {
+  if (!s || !x || !t || !m || !grad_dev || !loss_dev || n < 1) return LBM_EINVAL;
+  if (n > SG_NOALLOC_MAX_ROWS) return LBM_EINVAL;
+  if (!s->scratch) return LBM_EHIP;
+  float* p = s->scratch;
+  const Bufs b{p, p + SC_H, p + 4 * SC_H, p + 4 * SC_H + SC_O, p + 2 * SC_H, p + 3 * SC_H,
+               p + 4 * SC_H + 2 * SC_O, grad_dev, loss_dev};
+  return backward(s, x, t, m, n, b);
 }
 
 void sg_destroy(sg_ctx* s) {

@@ -122,8 +122,13 @@ _SIGNATURES = {
                                    ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
     "sg_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_int32, ctypes.c_float, ctypes.POINTER(ctypes.c_float)]),
+    "sg_gradient_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
     "sg_destroy": (None, [ctypes.c_void_p]),
 }
+
+SG_NOALLOC_MAX_ROWS = 1024
 
 
 def lib():
@@ -352,6 +357,15 @@ class Network:
                                  ctypes.c_void_p(m.data_ptr()), int(x.shape[0]), g.ctypes.data,
                                  ctypes.byref(loss)), "sg gradient")
         return g, float(loss.value)
+
+    def gradient_noalloc(self, x, t, m, grad, loss):
+        """The same gradient into caller-owned device tensors grad (float32,
+        n_params) and loss (float32, 1), with the library's fixed scratch
+        array; asynchronous, allocates nothing."""
+        _check(lib().sg_gradient_noalloc(self._ctx, ctypes.c_void_p(x.data_ptr()),
+                                         ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(m.data_ptr()),
+                                         int(x.shape[0]), ctypes.c_void_p(grad.data_ptr()),
+                                         ctypes.c_void_p(loss.data_ptr())), "sg gradient_noalloc")
 
     def train_step(self, x, t, m, lr: float) -> float:
         loss = ctypes.c_float()
