@@ -2,15 +2,20 @@
 FP64 path (itself parity-checked against the oracle) on the two larger
 droplet workloads.
 
-    python -m paper_1411_2181_amd.precision_study OUT.json [--c3-steps 10000]
+    python -m paper_1411_2181_amd.precision_study OUT.json [--c3-steps 50000] \
+        [--c3-lambdas 0.5,2] [--skip-c2]
 
 * 192x96x64 (W = 64), R = 16, polymer in the droplet (L^2 = 100, fraction
   0.4), lambda = 1, De in {0.5, 1, 2} x Ca in {0.1, 0.2} (Ca = 0.3 needs a
   wall speed above the 0.19 cap at the calibrated sigma), 20000 steps: the
   six runs advance as one batch per precision.
 * 512x256x128 (W = 128), R = 32, polymer in the matrix (L^2 = 400, De = 1,
-  fraction 0.4), lambda = 0.5, U_w = 0.1: deformation, orientation and the
-  relative L2 error of the velocity field at checkpoints.
+  fraction 0.4), U_w = 0.1, lambda = 0.5 (tau_A = 4/3, tau_B = 1.5) and
+  lambda = 2 (tau_A = 1.75, tau_B = 0.875: with 40 % of the matrix viscosity
+  in the polymer, lambda = 2 puts the matrix solvent below the
+  Laplace-calibrated tau window; every precision follows the same dynamics,
+  which is what this comparison needs): deformation, orientation and the
+  relative L2 error of the velocity field at checkpoints every 10000 steps.
 
 Reported per result: |D - D_64|, |theta - theta_64|, velocity rel. L2, mass
 drift per component.
@@ -41,10 +46,18 @@ def c2_runs():
     return runs, tags
 
 
-def c3_run():
+def c3_run(lam=0.5):
     import bench
     p, info = bench.workload_params()
-    return p, dict(Ca=info["Ca"], u_wall=p["u_wall"], tau=p["tau"], tau_P=p["tau_P"][1])
+    if lam != 0.5:
+        # same wall speed, tau_P and polymer; droplet and matrix solvents set
+        # for lambda = eta_A / eta_M with eta_M = eta_B / (1 - 0.4)
+        tau_A = 1.75
+        eta_A = physics.eta_of_tau(tau_A)
+        eta_M = eta_A / lam
+        tau_B = physics.tau_of_eta(0.6 * eta_M)
+        p = dict(p, tau=(tau_A, tau_B), eta_P=(0.0, 0.4 * eta_M))
+    return p, dict(lam=lam, u_wall=p["u_wall"], tau=p["tau"], tau_P=p["tau_P"][1])
 
 
 def twin(runs, steps, every, export_u_at=(), log=print, precisions=PRECISIONS):
@@ -62,6 +75,7 @@ def twin(runs, steps, every, export_u_at=(), log=print, precisions=PRECISIONS):
             b.step(k)
             done += k
             obs = b.observe()
+            log(f"  {prec} step {done}: D {[round(o['D'], 6) for o in obs][:3]}")
             hist.append([dict(step=o["step"], D=o["D"], theta=o["theta_deg"], mass=o["mass"],
                               status=o["status"]) for o in obs])
             if done in export_u_at:
@@ -100,28 +114,37 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("out")
     ap.add_argument("--c2-steps", type=int, default=20000)
-    ap.add_argument("--c3-steps", type=int, default=10000)
+    ap.add_argument("--c3-steps", type=int, default=50000)
+    ap.add_argument("--c3-lambdas", default="0.5,2")
+    ap.add_argument("--skip-c2", action="store_true")
     ap.add_argument("--precisions", default=",".join(PRECISIONS),
                     help="comma-separated subset (fp64 is always included)")
     args = ap.parse_args(argv)
     precs = tuple(dict.fromkeys(["fp64"] + args.precisions.split(",")))
     log = lambda s: print(s, flush=True)
-    report = {}
-    runs, tags = c2_runs()
-    tw = twin(runs, args.c2_steps, 2000, export_u_at=(args.c2_steps,), log=log, precisions=precs)
-    report["c2"] = dict(runs=tags, steps=args.c2_steps, compare=compare(tw, len(runs)),
-                        seconds={p: tw[p]["seconds"] for p in precs})
-    for row in report["c2"]["compare"]:
-        log(f"c2 {row['precision']} run {row['run']}: max|dD| {row['max_dD']:.2e} "
-            f"max|dtheta| {row['max_dtheta']:.2e} u rel L2 {row['u_rel_l2']}")
-    p3, tag3 = c3_run()
-    tw3 = twin([p3], args.c3_steps, 2000, export_u_at=(args.c3_steps // 2, args.c3_steps), log=log,
-               precisions=precs)
-    report["c3"] = dict(run=tag3, steps=args.c3_steps, compare=compare(tw3, 1),
-                        seconds={p: tw3[p]["seconds"] for p in precs})
-    for row in report["c3"]["compare"]:
-        log(f"c3 {row['precision']}: max|dD| {row['max_dD']:.2e} max|dtheta| {row['max_dtheta']:.2e} "
-            f"u rel L2 {row['u_rel_l2']}")
+    from .build import source_hash
+    report = {"source_hash": source_hash()}
+    if not args.skip_c2:
+        runs, tags = c2_runs()
+        tw = twin(runs, args.c2_steps, 2000, export_u_at=(args.c2_steps,), log=log, precisions=precs)
+        report["c2"] = dict(runs=tags, steps=args.c2_steps, compare=compare(tw, len(runs)),
+                            seconds={p: tw[p]["seconds"] for p in precs})
+        for row in report["c2"]["compare"]:
+            log(f"c2 {row['precision']} run {row['run']}: max|dD| {row['max_dD']:.2e} "
+                f"max|dtheta| {row['max_dtheta']:.2e} u rel L2 {row['u_rel_l2']}")
+    report["c3"] = []
+    ck = tuple(range(10000, args.c3_steps + 1, 10000)) or (args.c3_steps,)
+    for lam in (float(v) for v in args.c3_lambdas.split(",") if v):
+        p3, tag3 = c3_run(lam)
+        tw3 = twin([p3], args.c3_steps, 2000, export_u_at=ck, log=log, precisions=precs)
+        rep = dict(run=tag3, steps=args.c3_steps, compare=compare(tw3, 1),
+                   seconds={p: tw3[p]["seconds"] for p in precs})
+        report["c3"].append(rep)
+        for row in rep["compare"]:
+            log(f"c3 lambda {lam} {row['precision']}: max|dD| {row['max_dD']:.2e} "
+                f"max|dtheta| {row['max_dtheta']:.2e} u rel L2 {row['u_rel_l2']}")
+        with open(args.out, "w") as fh:
+            json.dump(report, fh, indent=1)
     with open(args.out, "w") as fh:
         json.dump(report, fh, indent=1)
     return 0
