@@ -131,14 +131,18 @@ typedef struct {
 } lbm_obs;
 
 /* Launch shape of the step kernel (chosen by the autotuner).  A tile is
- * bx * by columns of nodes advanced by two workgroups of bx * by threads
- * (one per component), which march up bz planes in z; persistent > 0 caps
- * the grid at that many workgroups (rounded down to a multiple of 16, at
- * least 16), which then loop over the tile table. */
+ * bx * by columns of nodes advanced by one workgroup of 2 * bx * by threads
+ * (one half per component), which marches up bz planes in z; persistent > 0
+ * caps the grid at that many workgroups (rounded down to a multiple of 8, at
+ * least 8), which then loop over the tile table.  The kernel reads a run's
+ * population arrays from one base when its 19 arrays of one component span
+ * less than 4 GiB, and from a base per group of four arrays otherwise;
+ * grouped = 1 takes the grouped addressing for every run (same results). */
 typedef struct {
-  int32_t bx, by;        /* (32,8) (64,4) (16,16), or (32,16) except FP64    */
+  int32_t bx, by;        /* (32,8) (16,16) (16,8) (8,16); FP64 (16,8) (8,16) */
   int32_t bz;            /* planes per tile, 1 <= bz <= 1024                 */
   int32_t persistent;    /* 0 = one workgroup per tile                        */
+  int32_t grouped;       /* 0 = as the run sizes need, 1 = always grouped     */
 } lbm_launch;
 
 typedef struct lbm_ctx lbm_ctx;

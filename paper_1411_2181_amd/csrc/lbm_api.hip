@@ -119,7 +119,7 @@ struct lbm_ctx {
   std::vector<int64_t> done;
   char* ws = nullptr;
   Layout L{};
-  lbm_launch launch{16, 8, 16, 0};
+  lbm_launch launch{16, 8, 16, 0, 0};
   int64_t ntiles = 0;          // entries of the (XCD-permuted) tile table
   std::map<int, hipGraphExec_t> graphs;
   std::map<int, hipGraph_t> graph_src;
@@ -154,7 +154,11 @@ lbm::StepArgs<T, S> step_args(const lbm_ctx* c) {
   a.bz = c->launch.bz;
   a.gstep = c->at<int32_t>(c->L.gstep);
   a.any_visc = 0;
-  for (const RunDev& R : c->runs) a.any_visc |= R.visc >= 0;
+  a.wide = c->launch.grouped;
+  for (const RunDev& R : c->runs) {
+    a.any_visc |= R.visc >= 0;
+    a.wide |= (int64_t)lbm::Q * R.ld * (int64_t)sizeof(S) >= (int64_t)1 << 32;
+  }
   return a;
 }
 
@@ -205,8 +209,8 @@ int validate(const lbm_params* p) {
   // with 32-bit byte offsets
   if (n * (int64_t)elem_S(p->precision) >= (int64_t)1 << 32) return LBM_EINVAL;
   if (n * (int64_t)elem_T(p->precision) >= (int64_t)1 << 32) return LBM_EINVAL;
-  // the 19 direction arrays of one component are addressed from one base
-  if (19 * ld_of(n) * (int64_t)elem_S(p->precision) >= (int64_t)1 << 32) return LBM_EINVAL;
+  // the step kernel addresses DG_WIDE direction arrays from one base
+  if (lbm::DG_WIDE * ld_of(n) * (int64_t)elem_S(p->precision) >= (int64_t)1 << 32) return LBM_EINVAL;
   if (!(std::fabs(p->u_wall) < 0.2)) return LBM_EINVAL;
   if (!(p->radius >= 0.0) || !(p->radius < 0.5 * p->nz)) return LBM_EINVAL;
   if (!(p->rho_major > 0.0) || !(p->rho_minor > 0.0)) return LBM_EINVAL;
@@ -544,6 +548,7 @@ int lbm_set_launch(lbm_ctx* c, const lbm_launch* in) {
   // block shapes with a compiled step-kernel instance for this precision
   const bool shape_ok = lbm::step_shape_ok(l.bx, l.by, c->prec == LBM_FP64);
   if (!shape_ok || l.bz < 1 || l.bz > 1024 || l.persistent < 0) return LBM_EINVAL;
+  if (l.grouped != 0 && l.grouped != 1) return LBM_EINVAL;
   const lbm_launch old = c->launch;
   c->launch = l;
   const int e = build_tiles(c);

@@ -25,6 +25,19 @@ __host__ __device__ constexpr T wgt(int i) {
   return WCLASS[i] == 0 ? T(1) / T(3) : (WCLASS[i] == 1 ? T(1) / T(18) : T(1) / T(36));
 }
 
+// c.v for a lattice vector c (components -1, 0, 1) over its nonzero
+// components only: with c known at compile time this is at most one add or
+// subtract (a sum started from 0 would keep a 0 + x, which is not x for -0).
+template <typename T>
+__device__ __forceinline__ T cdot(int cx, int cy, int cz, T x, T y, T z) {
+  T r = T(0);
+  bool any = false;
+  if (cx != 0) { r = cx > 0 ? x : -x; any = true; }
+  if (cy != 0) { r = any ? (cy > 0 ? r + y : r - y) : (cy > 0 ? y : -y); any = true; }
+  if (cz != 0) r = any ? (cz > 0 ? r + z : r - z) : (cz > 0 ? z : -z);
+  return r;
+}
+
 // ---- records -------------------------------------------------------------
 template <typename T>
 struct alignas(4 * sizeof(T)) V4 {
@@ -94,13 +107,18 @@ struct Store<T, T> {
   static constexpr bool kRandom = false;
   static constexpr double kScale = 1.0;
   static __device__ __forceinline__ T load(const T* p, int64_t k) { return p[k]; }
-  // store v (r: random word, unused here)
-  static __device__ __forceinline__ void put(T* p, int64_t k, T v, uint32_t /*r*/) {
+  // the stored form of v (r: random word, unused here), and its store
+  using Raw = T;
+  static __device__ __forceinline__ Raw encode(T v, uint32_t /*r*/) { return v; }
+  static __device__ __forceinline__ void write(T* p, int64_t k, Raw v) {
 #if LBM_NT_STORES
     __builtin_nontemporal_store(v, p + k);
 #else
     p[k] = v;
 #endif
+  }
+  static __device__ __forceinline__ void put(T* p, int64_t k, T v, uint32_t r) {
+    write(p, k, encode(v, r));
   }
   static __device__ __forceinline__ void store(T* p, int64_t k, T v) { put(p, k, v, 0u); }
 };
@@ -131,14 +149,22 @@ struct Store<float, __half> {
   // (|v| - lower)/spacing and the rounding error has zero mean.
   // Deterministic rounding leaves the same error at every node of a uniform
   // region, step after step, and that coherent bias accumulates in the flow.
-  static __device__ __forceinline__ void put(__half* p, int64_t k, float v, uint32_t r) {
+  // the FP16 bits (in the low half of a 32-bit register) and their store
+  using Raw = uint32_t;
+  static __device__ __forceinline__ Raw encode(float v, uint32_t r) {
 #if LBM_FP16_RN
     (void)r;
-    raw_store(p, k, __builtin_bit_cast(unsigned short, __float2half_rn(v)));
+    return __builtin_bit_cast(unsigned short, __float2half_rn(v));
 #else
     const half2v h = __builtin_amdgcn_cvt_sr_f16_f32(half2v{0, 0}, v, r, false);
-    raw_store(p, k, __builtin_bit_cast(unsigned short, h[0]));
+    return __builtin_bit_cast(uint32_t, h);
 #endif
+  }
+  static __device__ __forceinline__ void write(__half* p, int64_t k, Raw v) {
+    raw_store(p, k, (unsigned short)v);
+  }
+  static __device__ __forceinline__ void put(__half* p, int64_t k, float v, uint32_t r) {
+    write(p, k, encode(v, r));
   }
   static __device__ __forceinline__ void store(__half* p, int64_t k, float v) {
     raw_store(p, k, __builtin_bit_cast(unsigned short, __float2half_rn(v)));

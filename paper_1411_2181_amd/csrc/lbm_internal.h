@@ -15,7 +15,15 @@ struct StepArgs {
   int32_t bz;
   const int32_t* gstep;   // step index within the current step call
   int32_t any_visc;       // some run of the batch carries a polymer phase
+  int32_t wide;           // some run's 19 population arrays span >= 4 GiB
 };
+
+// Population addressing of the step kernel: direction i of a run is read
+// from a 64-bit base of its group of G direction arrays plus a 32-bit byte
+// offset, so G arrays of one run must span less than 4 GiB.  G = Q (one base
+// for all directions: fewest scalar registers) when a run's 19 arrays fit;
+// runs up to the library's limit use G = DG_WIDE.
+constexpr int DG_WIDE = 4;
 
 // Number of per-block partial values of the observable reduction.
 constexpr int NOBS = 16;

@@ -80,6 +80,17 @@ struct StepLds {
   T M[2][2][4][F::NT];        // planes mod 2, component: rho, j of the tile columns
 };
 
+// A whole record from LDS in one access: the lanes of a wave read records
+// 16 B (FP32) apart, and only full-width reads keep them on distinct banks
+// (a read of one or two of the four values would put 2-4 lanes on a bank).
+template <typename T>
+__device__ __forceinline__ V4<T> lds_v4(const V4<T>* p) {
+  typedef T vec4 __attribute__((ext_vector_type(4)));
+  typedef const volatile __attribute__((address_space(3))) vec4* lds_vec4;
+  const vec4 v = *(lds_vec4)p;
+  return V4<T>{v.x, v.y, v.z, v.w};
+}
+
 template <int BX, int BY, typename T>
 constexpr bool step_fits() { return sizeof(StepLds<T, BX, BY>) <= 160 * 1024; }
 
@@ -87,7 +98,8 @@ constexpr bool step_fits() { return sizeof(StepLds<T, BX, BY>) <= 160 * 1024; }
 // in the compute type).
 #define LBM_FOR_SHAPES(M) M(32, 8) M(16, 16) M(16, 8) M(8, 16)
 
-template <typename T, typename S, int BX, int BY>
+
+template <typename T, typename S, int BX, int BY, int DG>
 __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
   using F = Frame<BX, BY>;
   constexpr int NT = F::NT, NW = F::NW, HX1 = F::HX1, N1 = F::N1, HX2 = F::HX2, N2 = F::N2;
@@ -179,15 +191,21 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
     const uint32_t rowb[3] = {(uint32_t)(ym * nx) * SZ, (uint32_t)(yq * nx) * SZ,
                               (uint32_t)(yp * nx) * SZ};
     const uint32_t colb[3] = {(uint32_t)xm * SZ, (uint32_t)xq * SZ, (uint32_t)xp * SZ};
-    // byte offset of direction i's array from the component's first array
-    // (a component's 19 arrays span < 4 GiB, which the library checks)
+    // direction i's array: the base of its group of DG arrays (uniform,
+    // 64-bit) plus a 32-bit byte offset (i % DG) * db + position
     const uint32_t db = (uint32_t)N * SZ;
+    auto grp = [&](auto* base, int i) { return base + (int64_t)(i / DG * DG) * N; };
     const int own = yq * nx + xq;
 
     T raw[K2][8];    // densities and C of the 2-frame positions (next plane)
     T cst[K2][6];    // C of the plane being staged, kept for the C ring
     T jv[6];         // momenta of the 1-frame position (plane to finalise)
     T pops[Q];       // populations arriving at the own column (plane to collide)
+    // values of the iteration's global stores: their registers are held to
+    // the end of the iteration, so that none is overwritten while its store
+    // may still be reading it (which would wait for the store to finish)
+    T held[Q + 7];
+    typename St::Raw held_s[Q];
     T acc[3][3];     // stress divergence of the 1-frame position: planes r-1, r, r+1
 #pragma unroll
     for (int p = 0; p < 3; ++p)
@@ -216,20 +234,21 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
       for (int c = 0; c < 6; ++c) jv[c] = *boff(J_in + c * N, mo);
     };
     // populations arriving at the own column in plane zz: pulled from
-    // x - c_i, or the node's own opposite population where the link crosses
-    // a wall (the choice is uniform and made by selects)
+    // x - c_i, or the node's own opposite
+    // population where the link crosses the wall
     auto load_pops = [&](int zz) {
       const uint32_t ownb = (uint32_t)zz * pb + rowb[1] + colb[1];
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         const int zs = zz - CZ[i];
-        const uint32_t off = (uint32_t)zs * pb + rowb[1 - CY[i]] + colb[1 - CX[i]];
-        if (CZ[i] == 0) {
-          pops[i] = St::load(boff(fs, (uint32_t)i * db + off), 0);
-        } else {
+        const S* src = grp(fs, i);
+        uint32_t off = (uint32_t)(i % DG) * db + ((uint32_t)zs * pb + rowb[1 - CY[i]] + colb[1 - CX[i]]);
+        if (CZ[i] != 0) {
           const bool in = zs >= 0 && zs < nz;
-          pops[i] = St::load(boff(fs, (uint32_t)(in ? i : OPPI[i]) * db + (in ? off : ownb)), 0);
+          src = in ? src : grp(fs, OPPI[i]);
+          off = in ? off : (uint32_t)(OPPI[i] % DG) * db + ownb;
         }
+        pops[i] = St::load(boff(src, off), 0);
       }
     };
 
@@ -265,71 +284,94 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
     };
 
     // ---- phase X: collide and stream component s into plane q of the own
-    // column
-    auto collide = [&](int q) {
+    // column.  The arithmetic runs in every iteration (on clamped or stale
+    // values outside the tile's planes, and for the columns of a ragged tile
+    // past the lattice), so that the populations loaded for it are consumed
+    // on every path; only ok (a plane of the tile, an active column) stores.
+    auto collide = [&](int q, bool ok) {
       const int n = q * nxy + own;
       const uint32_t nb = (uint32_t)n * SZ;
       const int slq = (q + 3) % 3, slm = (q + 2) % 3, slp = (q + 4) % 3;
       const int sm2 = q & 1;
       const T rx = L.M[sm2][s][0][oc];
       const T jx0 = L.M[sm2][s][1][oc], jx1 = L.M[sm2][s][2][oc], jx2 = L.M[sm2][s][3][oc];
-      T drho = 0, dj0 = 0, dj1 = 0, dj2 = 0;
+      // the destination's part of the re-reference, k_i = 3 c_i.j(x), once
+      // per pair of opposite directions (odd i; its opposite is i + 1)
+      const T j30 = T(3) * jx0, j31 = T(3) * jx1, j32 = T(3) * jx2;
+      T k3[Q];
+      T drho = T(0), dj0 = T(0), dj1 = T(0), dj2 = T(0);
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        int sl = slq, src = lc - CY[i] * HX1 - CX[i];
+        k3[i] = (i & 1) ? cdot(CX[i], CY[i], CZ[i], j30, j31, j32) : (i ? -k3[i - 1] : T(0));
+        int sl = CZ[i] == 0 ? slq : (CZ[i] > 0 ? slm : slp);
+        int src = lc - CY[i] * HX1 - CX[i];
         T sg = T(1), wall = T(0);
         if (CZ[i] != 0) {
-          // links through z: the pulled value, or (where the link crosses a
-          // wall) the half-way bounce-back of x's own population in
-          // o = opp(i), with c_o = -c_i and the moving-wall term
-          // -6 w_o rho c_o.u_wall
+          // the pulled value, or (where the link crosses a wall) the
+          // half-way bounce-back of x's own population in o = opp(i), with
+          // c_o = -c_i and the moving-wall term -6 w_o rho c_o.u_wall
           const int zs = q - CZ[i];
           const bool in = zs >= 0 && zs < nz;
           const int o = OPPI[i];
-          sl = in ? (CZ[i] > 0 ? slm : slp) : slq;
+          sl = in ? sl : slq;
           src = in ? src : lc;
           sg = in ? T(1) : T(-1);
           const T uwall = CZ[o] > 0 ? uw : -uw;
           wall = in ? T(0) : ((T(6) * kS * wgt<T>(o)) * rx) * (T(CX[o]) * uwall);
         }
-        const V4<T> r0 = L.rec[sl][s][0][src], r1 = L.rec[sl][s][1][src];
-        T cP = 0, cu = 0, cj = 0;
-        if (CX[i] != 0) { cP += T(CX[i]) * r0.y; cu += T(CX[i]) * r1.x; cj += T(CX[i]) * jx0; }
-        if (CY[i] != 0) { cP += T(CY[i]) * r0.z; cu += T(CY[i]) * r1.y; cj += T(CY[i]) * jx1; }
-        if (CZ[i] != 0) { cP += T(CZ[i]) * r0.w; cu += T(CZ[i]) * r1.z; cj += T(CZ[i]) * jx2; }
-        cP *= sg;
-        cu *= sg;
-        const T e = (r0.x - rx) + T(3) * (cP - cj) + r1.w * cu * cu;
-        const T h = om1 * pops[i] + (wgt<T>(i) * kS) * e - wall;
+        const V4<T> r0 = lds_v4(&L.rec[sl][s][0][src]), r1 = lds_v4(&L.rec[sl][s][1][src]);
+        // e = (f*_i(source) in units of w_i, less the destination's shift)
+        //   = (a - rho(x)) + 3 c.P - k_i + b (c.u^eq)^2
+        T e = r0.x - rx;
+        if (i != 0) {
+          T cP = cdot(CX[i], CY[i], CZ[i], r0.y, r0.z, r0.w);
+          T cu = cdot(CX[i], CY[i], CZ[i], r1.x, r1.y, r1.z);
+          if (CZ[i] != 0) { cP = sg * cP; cu = sg * cu; }
+          e = e + (T(3) * cP - k3[i]) + r1.w * cu * cu;
+        }
+        T h = om1 * pops[i] + (wgt<T>(i) * kS) * e;
+        if (CZ[i] != 0) h = h - wall;
         pops[i] = h;
-        drho += h;
-        if (CX[i] != 0) dj0 += T(CX[i]) * h;
-        if (CY[i] != 0) dj1 += T(CY[i]) * h;
-        if (CZ[i] != 0) dj2 += T(CZ[i]) * h;
+        drho = i == 0 ? h : drho + h;
+        if (CX[i] != 0) dj0 = i == 1 ? h : dj0 + T(CX[i]) * h;
+        if (CY[i] != 0) dj1 = i == 3 ? h : dj1 + T(CY[i]) * h;
+        if (CZ[i] != 0) dj2 = i == 5 ? h : dj2 + T(CZ[i]) * h;
       }
       // new moments; stored values against them.  FP16 rounding takes a
       // random word per value: a hash of (node, component, step) starts a
       // Weyl sequence over the directions (independent of the tile shape and
       // batch layout, and reproducible).
-      const T rnew = rx + drho * ikS;
-      const T jn0 = jx0 + dj0 * ikS, jn1 = jx1 + dj1 * ikS, jn2 = jx2 + dj2 * ikS;
+      T& rnew = held[Q];
+      T& jn0 = held[Q + 1];
+      T& jn1 = held[Q + 2];
+      T& jn2 = held[Q + 3];
+      rnew = rx + drho * ikS;
+      jn0 = jx0 + dj0 * ikS;
+      jn1 = jx1 + dj1 * ikS;
+      jn2 = jx2 + dj2 * ikS;
       uint32_t hb = 0;
       if (St::kRandom) hb = fmix32((uint32_t)n * 0x9e3779b1u ^ hstep);
+      T cd = T(0);   // c_i.dj, shared by the two directions of a pair
+      T* out = held;
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        T cd = 0;
-        if (CX[i] != 0) cd += T(CX[i]) * dj0;
-        if (CY[i] != 0) cd += T(CY[i]) * dj1;
-        if (CZ[i] != 0) cd += T(CZ[i]) * dj2;
-        const T out = pops[i] - wgt<T>(i) * (drho + T(3) * cd);
-        St::put(boff(fo, (uint32_t)i * db + nb), 0, out, hb + (uint32_t)i * 0x9e3779b9u);
+        if (i & 1) cd = cdot(CX[i], CY[i], CZ[i], dj0, dj1, dj2);
+        out[i] = i == 0 ? pops[i] - wgt<T>(i) * drho
+                        : pops[i] - wgt<T>(i) * (drho + T(3) * ((i & 1) ? cd : -cd));
       }
-      const uint32_t no = (uint32_t)n * TB;
-      *boff(rho_out, no) = rnew;
-      *boff(j_out, no) = jn0;
-      *boff(j_out + N, no) = jn1;
-      *boff(j_out + 2 * N, no) = jn2;
-      if (!isfinite(rnew + jn0 + jn1 + jn2)) st |= ST_NAN;
+      if (ok) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          held_s[i] = St::encode(out[i], hb + (uint32_t)i * 0x9e3779b9u);
+          St::write(boff(grp(fo, i), (uint32_t)(i % DG) * db + nb), 0, held_s[i]);
+        }
+        const uint32_t no = (uint32_t)n * TB;
+        *boff(rho_out, no) = rnew;
+        *boff(j_out, no) = jn0;
+        *boff(j_out + N, no) = jn1;
+        *boff(j_out + 2 * N, no) = jn2;
+        if (!isfinite(rnew + jn0 + jn1 + jn2)) st |= ST_NAN;
+      }
     };
 
     // ---- phase X: FENE-P for this thread's C components at plane q of the own
@@ -337,7 +379,7 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
     // first-order upwind A and S_kl = sum_m C_km G_ml + G_mk C_ml.  Ghost
     // planes: C zero-gradient (the clamped planes of the ring), u extrapolated
     // through the wall velocity, u(-1) = 2 u_bot - u(0), u(nz) = 2 u_top - u(nz-1).
-    auto fene = [&](int q, auto half) {
+    auto fene = [&](int q, auto half, bool ok) {
       constexpr int base = decltype(half)::value * 3;
       const int n = q * nxy + own;
       const int su = (q + 3) % 3, sum_ = (q + 2) % 3, sup = (q + 4) % 3;
@@ -359,7 +401,7 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
 #pragma unroll
       for (int i = 0; i < 6; ++i) c[i] = L.C[sc][i][lc];
       const double tr = (double)c[0] + (double)c[1] + (double)c[2];
-      if (base == 0 && tr >= L2) st |= ST_FENE;
+      if (ok && base == 0 && tr >= L2) st |= ST_FENE;
       const T fP = L2m3 * rcpT(T(L2 - tr));
       const T ua0 = u0 > T(0) ? u0 : T(0), ub0 = u0 < T(0) ? u0 : T(0);
       const T ua1 = u1 > T(0) ? u1 : T(0), ub1 = u1 < T(0) ? u1 : T(0);
@@ -367,25 +409,28 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
       constexpr int KK[6] = {0, 1, 2, 0, 0, 1};
       constexpr int LL[6] = {0, 1, 2, 1, 2, 2};
       constexpr int SYM[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
-      T csum = 0;
+      T* cn = held + Q + 4;
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) {
         const int k = base + kk;
         const T ck = c[k];
-        T adv = 0;
-        adv += ua0 * (ck - L.C[sc][k][lc - 1]) + ub0 * (L.C[sc][k][lc + 1] - ck);
+        T adv = ua0 * (ck - L.C[sc][k][lc - 1]) + ub0 * (L.C[sc][k][lc + 1] - ck);
         adv += ua1 * (ck - L.C[sc][k][lc - HX1]) + ub1 * (L.C[sc][k][lc + HX1] - ck);
         adv += ua2 * (ck - L.C[scm][k][lc]) + ub2 * (L.C[scp][k][lc] - ck);
-        T Sk = 0;
+        T Sk = c[SYM[KK[k]][0]] * Gm[0][LL[k]] + Gm[0][KK[k]] * c[SYM[0][LL[k]]];
 #pragma unroll
-        for (int mm = 0; mm < 3; ++mm)
+        for (int mm = 1; mm < 3; ++mm)
           Sk += c[SYM[KK[k]][mm]] * Gm[mm][LL[k]] + Gm[mm][KK[k]] * c[SYM[mm][LL[k]]];
         const T delta = k < 3 ? T(1) : T(0);
-        const T cn = ck + (-adv + Sk - (fP * ck - delta) * itP);
-        *boff(C_out + k * N, (uint32_t)n * TB) = cn;
-        csum += cn;
+        cn[kk] = ck + (-adv + Sk - (fP * ck - delta) * itP);
       }
-      if (!isfinite(csum)) st |= ST_NAN;
+      if (ok) {
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+          *boff(C_out + (base + kk) * N, (uint32_t)n * TB) = cn[kk];
+        }
+        if (!isfinite(cn[0] + cn[1] + cn[2])) st |= ST_NAN;
+      }
     };
 
     // ---- phase Y: stage C of plane r; stress-divergence terms of plane r ------
@@ -520,12 +565,11 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
       // unconditionally
       load_raw(r + 1);
       const int q = r - 3;
-      if (q >= z0 && q < zend && active) {
-        collide(q);
-        if (visc) {
-          if (s) fene(q, std::integral_constant<int, 1>{});
-          else fene(q, std::integral_constant<int, 0>{});
-        }
+      const bool ok = q >= z0 && q < zend && active;
+      collide(q, ok);
+      if (visc) {
+        if (s) fene(q, std::integral_constant<int, 1>{}, ok);
+        else fene(q, std::integral_constant<int, 0>{}, ok);
       }
       load_pops(clampz(r - 2, nz));
       __syncthreads();   // (2) plane r staged, plane r-3 collided
@@ -534,6 +578,10 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
       if (m >= z0 - 1 && m <= zend && m >= 0 && m < nz) finalise(m);
       shift_acc();
       load_j(r);
+#pragma unroll
+      for (int i = Q; i < Q + 7; ++i) asm volatile("" ::"v"(held[i]));
+#pragma unroll
+      for (int i = 0; i < Q; ++i) asm volatile("" ::"v"(held_s[i]));
     }
     if (st) atomicOr(a.P.status + tl.run, st);
   }
@@ -626,7 +674,10 @@ bool step_shape_ok(int bx, int by, bool fp64) {
 
 template <typename T, typename S, int BX, int BY>
 void launch_step_shape(const StepArgs<T, S>& a, dim3 grid, hipStream_t st) {
-  if constexpr (step_fits<BX, BY, T>()) k_step<T, S, BX, BY><<<grid, dim3(BX, BY, 2), 0, st>>>(a);
+  if constexpr (step_fits<BX, BY, T>()) {
+    if (a.wide) k_step<T, S, BX, BY, DG_WIDE><<<grid, dim3(BX, BY, 2), 0, st>>>(a);
+    else k_step<T, S, BX, BY, Q><<<grid, dim3(BX, BY, 2), 0, st>>>(a);
+  }
 }
 
 template <typename T, typename S>

@@ -73,7 +73,7 @@ class LbmObs(ctypes.Structure):
 
 class LbmLaunch(ctypes.Structure):
     _fields_ = [("bx", ctypes.c_int32), ("by", ctypes.c_int32), ("bz", ctypes.c_int32),
-                ("persistent", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("grouped", ctypes.c_int32)]
 
 
 _lib = None
@@ -279,10 +279,10 @@ class Batch:
     def launch(self) -> dict:
         l = LbmLaunch()
         _check(lib().lbm_get_launch(self._c(), ctypes.byref(l)), "get_launch")
-        return dict(bx=l.bx, by=l.by, bz=l.bz, persistent=l.persistent)
+        return dict(bx=l.bx, by=l.by, bz=l.bz, persistent=l.persistent, grouped=l.grouped)
 
-    def set_launch(self, bx=16, by=8, bz=16, persistent=0):
-        l = LbmLaunch(bx, by, bz, persistent)
+    def set_launch(self, bx=16, by=8, bz=16, persistent=0, grouped=0):
+        l = LbmLaunch(bx, by, bz, persistent, grouped)
         _check(lib().lbm_set_launch(self._c(), ctypes.byref(l)), "set_launch")
 
     def close(self):

@@ -91,13 +91,18 @@ def test_valid_parameters_and_workspace_size(L):
 
 
 def test_population_array_must_fit_32bit_offsets(L):
-    """One run's population array is addressed with 32-bit byte offsets:
-    1024 x 1024 x 600 nodes fit as FP32 (2.5 GB) but not as FP64 (5 GB)."""
+    """The step kernel addresses the population arrays of one run in groups of
+    four directions, with 32-bit byte offsets from a group's base: four arrays
+    must span less than 4 GiB.  1024 x 1024 x 200 nodes (4 x 0.84 GB in FP32)
+    fit in FP32 and FP16 but not in FP64; 1024 x 1024 x 300 only in FP16."""
     from paper_1411_2181_amd import lbmve
-    d = WL.base_params(nx=1024, ny=1024, nz=600, radius=8.0)
+    d = WL.base_params(nx=1024, ny=1024, nz=200, radius=8.0)
     assert L.lbm_validate(ctypes.byref(lbmve.make_params(d, "fp32"))) == 0
     assert L.lbm_validate(ctypes.byref(lbmve.make_params(d, "fp16s"))) == 0
     assert L.lbm_validate(ctypes.byref(lbmve.make_params(d, "fp64"))) == lbmve.LBM_EINVAL
+    d = WL.base_params(nx=1024, ny=1024, nz=300, radius=8.0)
+    assert L.lbm_validate(ctypes.byref(lbmve.make_params(d, "fp32"))) == lbmve.LBM_EINVAL
+    assert L.lbm_validate(ctypes.byref(lbmve.make_params(d, "fp16s"))) == 0
 
 
 def test_batch_requires_one_precision(L):

@@ -141,6 +141,27 @@ def test_launch_shapes_bit_identical(lbm):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16s"])
+def test_grouped_addressing_bit_identical(lbm, precision):
+    """The population arrays addressed in groups of four (the path of runs
+    whose arrays span more than 4 GiB) give the same bits as one base, on a
+    ragged lattice with walls and a polymer phase."""
+    d = WL.base_params(nx=37, ny=21, nz=19, radius=6.0, u_wall=0.05, tau=(1.0, 0.8),
+                       tau_P=(1.0, 5.0), eta_P=(0.0, 0.05), L2=(100.0, 100.0))
+    print(f"case grouped addressing 37x21x19 {precision}", flush=True)
+    out = []
+    for grouped in (0, 1):
+        s = lbm.Solver(d, precision)
+        shape = dict(bx=16, by=8, bz=7) if precision == "fp64" else dict(bx=32, by=8, bz=7)
+        s.set_launch(**shape, grouped=grouped)
+        assert s.launch["grouped"] == grouped
+        s.step(40)
+        out.append((s.export("f"), s.export("C"), s.export("rho")))
+        s.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16s"])
 def test_repeat_and_checkpoint_bit_identical(lbm, precision):
     d = WL.small_matrix_viscoelastic()
     a = lbm.Solver(d, precision)
@@ -421,6 +442,41 @@ def test_full_size_one_step_sampled(lbm, precision, tol):
         print(f"  column ({x}, {y}): f {ef:.1e}, C {eC:.1e}", flush=True)
         assert o.status == 0
         assert ef <= tol and eC <= tolC, (x, y, ef, eC)
+
+
+@pytest.mark.timeout(600)
+def test_wide_run_one_step_sampled(lbm):
+    """A run whose 19 population arrays of one component span more than
+    4 GiB (FP64, 400 x 384 x 192 = 29.5 M nodes: 4.5 GiB) takes the grouped
+    addressing by itself; one step checked against the oracle on sampled
+    columns (droplet, interface, tile seams, periodic edges)."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    p = dict(bench.workload_params()[0], nx=400, ny=384, nz=192)   # the R = 32 droplet
+    nx, ny = p["nx"], p["ny"]
+    assert 19 * nx * ny * p["nz"] * 8 > 1 << 32
+    print(f"case wide run {nx}x{ny}x{p['nz']} fp64", flush=True)
+    s = lbm.Solver(p, "fp64")
+    s.set_launch(bx=16, by=8, bz=64, persistent=0)
+    assert s.launch["grouped"] == 0      # chosen per run size inside the library
+    s.step(20)
+    f0, C0 = s.export("f"), s.export("C")
+    s.step(1)
+    f1, C1 = s.export("f"), s.export("C")
+    s.close()
+    fmax, cmax = max(f1.max(), -f1.min()), max(C1.max(), -C1.min())
+    for x, y in [(199, 191), (200, 192), (168, 192), (232, 191), (15, 7), (16, 8),
+                 (0, 0), (399, 383), (100, 300)]:
+        o = Oracle(dict(p, nx=9, ny=9), f=_column_block(f0, x, y, nx, ny),
+                   C=_column_block(C0, x, y, nx, ny))
+        o.step(1)
+        ef = np.abs(o.f[..., 4, 4] - f1[..., y, x]).max() / fmax
+        eC = np.abs(o.C[..., 4, 4] - C1[..., y, x]).max() / cmax
+        print(f"  column ({x}, {y}): f {ef:.1e}, C {eC:.1e}", flush=True)
+        assert o.status == 0
+        assert ef <= 1e-12 and eC <= 1e-12, (x, y, ef, eC)
 
 
 @pytest.mark.parametrize("eta", [(0.0, 0.0), (0.0, 0.05)])
