@@ -108,6 +108,9 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
   __shared__ StepLds<T, BX, BY> L;
   using St = Store<T, S>;
   const T kS = T(St::kScale), ikS = T(1.0 / St::kScale);
+  constexpr bool kHalf = std::is_same<S, __half>::value;
+  constexpr int kPopsEarly = kHalf ? Q : 8;     // population loads before barrier (2)
+  constexpr bool kMomentsLate = !kHalf;         // moment and C stores after it
   const int g = *a.gstep;
   // every wave lies in one threadIdx.z half (bx * by is a multiple of 64),
   // so the component index is wave-uniform: read it as a scalar, which keeps
@@ -236,10 +239,12 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
     // populations arriving at the own column in plane zz: pulled from
     // x - c_i, or the node's own opposite
     // population where the link crosses the wall
-    auto load_pops = [&](int zz) {
+    auto load_pops = [&](int zz, auto lo_c, auto hi_c) {
+      constexpr int lo = decltype(lo_c)::value, hi = decltype(hi_c)::value;
       const uint32_t ownb = (uint32_t)zz * pb + rowb[1] + colb[1];
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
+        if (i < lo || i >= hi) continue;
         const int zs = zz - CZ[i];
         const S* src = grp(fs, i);
         uint32_t off = (uint32_t)(i % DG) * db + ((uint32_t)zs * pb + rowb[1 - CY[i]] + colb[1 - CX[i]]);
@@ -280,6 +285,22 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
 #pragma unroll
           for (int c = 0; c < 6; ++c) cst[k][c] = raw[k][2 + c];
         }
+      }
+    };
+
+    // the new moments (and with withC the new C) of plane q, from the
+    // registers that hold them since the collision and FENE-P update
+    auto store_moments = [&](int q, bool withC) {
+      const uint32_t no = (uint32_t)(q * nxy + own) * TB;
+      *boff(rho_out, no) = held[Q];
+      *boff(j_out, no) = held[Q + 1];
+      *boff(j_out + N, no) = held[Q + 2];
+      *boff(j_out + 2 * N, no) = held[Q + 3];
+      if (!isfinite(held[Q] + held[Q + 1] + held[Q + 2] + held[Q + 3])) st |= ST_NAN;
+      if (withC && visc) {
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) *boff(C_out + (3 * s + kk) * N, no) = held[Q + 4 + kk];
+        if (!isfinite(held[Q + 4] + held[Q + 5] + held[Q + 6])) st |= ST_NAN;
       }
     };
 
@@ -359,18 +380,15 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
         out[i] = i == 0 ? pops[i] - wgt<T>(i) * drho
                         : pops[i] - wgt<T>(i) * (drho + T(3) * ((i & 1) ? cd : -cd));
       }
+      // encoded on every path (a value kept only where stored would be a
+      // loop-carried merge: register copies in every iteration)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) held_s[i] = St::encode(out[i], hb + (uint32_t)i * 0x9e3779b9u);
       if (ok) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          held_s[i] = St::encode(out[i], hb + (uint32_t)i * 0x9e3779b9u);
+        for (int i = 0; i < Q; ++i)
           St::write(boff(grp(fo, i), (uint32_t)(i % DG) * db + nb), 0, held_s[i]);
-        }
-        const uint32_t no = (uint32_t)n * TB;
-        *boff(rho_out, no) = rnew;
-        *boff(j_out, no) = jn0;
-        *boff(j_out + N, no) = jn1;
-        *boff(j_out + 2 * N, no) = jn2;
-        if (!isfinite(rnew + jn0 + jn1 + jn2)) st |= ST_NAN;
+        if (!kMomentsLate) store_moments(q, false);
       }
     };
 
@@ -381,7 +399,6 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
     // through the wall velocity, u(-1) = 2 u_bot - u(0), u(nz) = 2 u_top - u(nz-1).
     auto fene = [&](int q, auto half, bool ok) {
       constexpr int base = decltype(half)::value * 3;
-      const int n = q * nxy + own;
       const int su = (q + 3) % 3, sum_ = (q + 2) % 3, sup = (q + 4) % 3;
       const int sc = q & 3, scm = (q + 3) & 3, scp = (q + 1) & 3;
       const T u0 = L.u[su][0][lc], u1 = L.u[su][1][lc], u2 = L.u[su][2][lc];
@@ -424,11 +441,10 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
         const T delta = k < 3 ? T(1) : T(0);
         cn[kk] = ck + (-adv + Sk - (fP * ck - delta) * itP);
       }
-      if (ok) {
+      if (!kMomentsLate && ok) {
+        const uint32_t no = (uint32_t)(q * nxy + own) * TB;
 #pragma unroll
-        for (int kk = 0; kk < 3; ++kk) {
-          *boff(C_out + (base + kk) * N, (uint32_t)n * TB) = cn[kk];
-        }
+        for (int kk = 0; kk < 3; ++kk) *boff(C_out + (base + kk) * N, no) = cn[kk];
         if (!isfinite(cn[0] + cn[1] + cn[2])) st |= ST_NAN;
       }
     };
@@ -556,7 +572,7 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
     const int z0 = tl.z0, zend = min(tl.z0 + a.bz, nz);
     load_raw(z0 - 2);
     load_j(z0 - 3);
-    load_pops(clampz(z0 - 4, nz));
+    load_pops(clampz(z0 - 4, nz), std::integral_constant<int, 0>{}, std::integral_constant<int, Q>{});
     for (int r = z0 - 2; r <= zend + 2; ++r) {
       __syncthreads();   // (1) readers of the previous iteration are done
       ingest(r);
@@ -571,17 +587,30 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
         if (s) fene(q, std::integral_constant<int, 1>{}, ok);
         else fene(q, std::integral_constant<int, 0>{}, ok);
       }
-      load_pops(clampz(r - 2, nz));
+      // the next plane's populations load in two parts, one on each side of
+      // the barrier, and the moments and C are stored after it: the memory
+      // requests spread over the iteration (measured faster in FP32 and
+      // FP64; with FP16 storage the loads stay in phase X and the moments
+      // and C are stored where they are computed)
+      load_pops(clampz(r - 2, nz), std::integral_constant<int, 0>{},
+                std::integral_constant<int, kPopsEarly>{});
       __syncthreads();   // (2) plane r staged, plane r-3 collided
+      if (kMomentsLate && ok) store_moments(q, true);
+      load_pops(clampz(r - 2, nz), std::integral_constant<int, kPopsEarly>{},
+                std::integral_constant<int, Q>{});
       stage_c_and_divergence(r);
       const int m = r - 1;
       if (m >= z0 - 1 && m <= zend && m >= 0 && m < nz) finalise(m);
       shift_acc();
       load_j(r);
 #pragma unroll
-      for (int i = Q; i < Q + 7; ++i) asm volatile("" ::"v"(held[i]));
-#pragma unroll
       for (int i = 0; i < Q; ++i) asm volatile("" ::"v"(held_s[i]));
+#pragma unroll
+      for (int i = Q; i < Q + 4; ++i) asm volatile("" ::"v"(held[i]));
+      if (visc) {
+#pragma unroll
+        for (int i = Q + 4; i < Q + 7; ++i) asm volatile("" ::"v"(held[i]));
+      }
     }
     if (st) atomicOr(a.P.status + tl.run, st);
   }
