@@ -140,7 +140,8 @@ typedef struct {
  * grouped = 1 takes the grouped addressing for every run (same results). */
 typedef struct {
   int32_t bx, by;        /* (32,8) (16,16) (16,8) (8,16); FP64 (16,8) (8,16) */
-  int32_t bz;            /* planes per tile, 1 <= bz <= 1024                 */
+  int32_t bz;            /* planes per tile, 1 <= bz <= 1024; 0: each tile
+                            spans its run's whole height                      */
   int32_t persistent;    /* 0 = one workgroup per tile                        */
   int32_t grouped;       /* 0 = as the run sizes need, 1 = always grouped     */
 } lbm_launch;

@@ -19,7 +19,7 @@ CACHE = os.path.join(_HERE, "autotune_cache.json")
 SHAPES = [(32, 8), (16, 16), (16, 8), (8, 16)]
 # the FP64 rings of the 512-thread tiles exceed the LDS
 SHAPES_FP64 = [(16, 8), (8, 16)]
-BZ = [16, 32, 64, 128]
+BZ = [16, 32, 64, 128]      # planes per tile; 0 (also tried): whole columns
 PERSISTENT = [1024, 2048]
 
 
@@ -27,8 +27,8 @@ def candidates(nz_max: int, precision: str = "fp32"):
     shapes = SHAPES_FP64 if precision == "fp64" else SHAPES
     out = []
     for bx, by in shapes:
-        for bz in BZ:
-            if bz <= max(8, nz_max):
+        for bz in BZ + [0]:
+            if bz <= max(8, nz_max) and not (bz == 0 and nz_max in BZ):
                 out.append(dict(bx=bx, by=by, bz=bz, persistent=0))
     return out
 

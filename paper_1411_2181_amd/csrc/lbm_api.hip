@@ -151,7 +151,6 @@ lbm::StepArgs<T, S> step_args(const lbm_ctx* c) {
   a.runs = c->at<RunDev>(c->L.runs);
   a.tiles = c->at<Tile>(c->L.tiles);
   a.ntiles = (int32_t)c->ntiles;
-  a.bz = c->launch.bz;
   a.gstep = c->at<int32_t>(c->L.gstep);
   a.any_visc = 0;
   a.wide = c->launch.grouped;
@@ -302,9 +301,11 @@ int build_tiles(lbm_ctx* c) {
   std::vector<Tile> canon;
   for (int r = 0; r < c->nruns; ++r) {
     const RunDev& R = c->runs[r];
-    for (int z = 0; z < R.nz; z += l.bz)
+    const int bzr = l.bz > 0 ? l.bz : R.nz;   // bz = 0: whole columns
+    for (int z = 0; z < R.nz; z += bzr)
       for (int y = 0; y < R.ny; y += l.by)
-        for (int x = 0; x < R.nx; x += l.bx) canon.push_back(Tile{r, x, y, z});
+        for (int x = 0; x < R.nx; x += l.bx)
+          canon.push_back(Tile{r, x, y, z, std::min(z + bzr, R.nz)});
   }
   const int64_t T = (int64_t)canon.size();
   const int64_t Tp = (T + 7) / 8 * 8;
@@ -313,7 +314,7 @@ int build_tiles(lbm_ctx* c) {
   const int64_t per = Tp / 8;
   for (int64_t p = 0; p < Tp; ++p) {
     const int64_t cidx = (p % 8) * per + p / 8;
-    table[p] = cidx < T ? canon[cidx] : Tile{-1, 0, 0, 0};
+    table[p] = cidx < T ? canon[cidx] : Tile{-1, 0, 0, 0, 0};
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   HIPCHK(hipMemcpy(c->at<Tile>(c->L.tiles), table.data(), Tp * sizeof(Tile), hipMemcpyHostToDevice));
@@ -547,7 +548,7 @@ int lbm_set_launch(lbm_ctx* c, const lbm_launch* in) {
   const lbm_launch l = *in;
   // block shapes with a compiled step-kernel instance for this precision
   const bool shape_ok = lbm::step_shape_ok(l.bx, l.by, c->prec == LBM_FP64);
-  if (!shape_ok || l.bz < 1 || l.bz > 1024 || l.persistent < 0) return LBM_EINVAL;
+  if (!shape_ok || l.bz < 0 || l.bz > 1024 || l.persistent < 0) return LBM_EINVAL;
   if (l.grouped != 0 && l.grouped != 1) return LBM_EINVAL;
   const lbm_launch old = c->launch;
   c->launch = l;

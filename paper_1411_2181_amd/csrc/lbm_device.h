@@ -66,9 +66,9 @@ struct RunDev {
 };
 
 // One tile of the step launch: a bx*by column block at (x0, y0) covering
-// z0 .. z0+bz-1 of run `run` (run < 0: padding entry, skipped).
+// planes z0 .. z1-1 of run `run` (run < 0: padding entry, skipped).
 struct Tile {
-  int32_t run, x0, y0, z0;
+  int32_t run, x0, y0, z0, z1;
 };
 
 // ---- storage conversions -------------------------------------------------
@@ -156,7 +156,9 @@ struct Store<float, __half> {
     (void)r;
     return __builtin_bit_cast(unsigned short, __float2half_rn(v));
 #else
-    const half2v h = __builtin_amdgcn_cvt_sr_f16_f32(half2v{0, 0}, v, r, false);
+    // the conversion writes the low half of a register; the high half keeps
+    // the bits of v (not stored), which spares clearing a register first
+    const half2v h = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(half2v, v), v, r, false);
     return __builtin_bit_cast(uint32_t, h);
 #endif
   }

@@ -12,7 +12,6 @@ struct StepArgs {
   const RunDev* runs;
   const Tile* tiles;
   int32_t ntiles;
-  int32_t bz;
   const int32_t* gstep;   // step index within the current step call
   int32_t any_visc;       // some run of the batch carries a polymer phase
   int32_t wide;           // some run's 19 population arrays span >= 4 GiB

@@ -569,7 +569,7 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
       }
     };
 
-    const int z0 = tl.z0, zend = min(tl.z0 + a.bz, nz);
+    const int z0 = tl.z0, zend = tl.z1;
     load_raw(z0 - 2);
     load_j(z0 - 3);
     load_pops(clampz(z0 - 4, nz), std::integral_constant<int, 0>{}, std::integral_constant<int, Q>{});

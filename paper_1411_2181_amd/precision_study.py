@@ -117,6 +117,8 @@ def main(argv=None):
     ap.add_argument("--c3-steps", type=int, default=50000)
     ap.add_argument("--c3-lambdas", default="0.5,2")
     ap.add_argument("--skip-c2", action="store_true")
+    ap.add_argument("--resume", default=None,
+                    help="earlier report of the same sources: keep its parts, run the missing ones")
     ap.add_argument("--precisions", default=",".join(PRECISIONS),
                     help="comma-separated subset (fp64 is always included)")
     args = ap.parse_args(argv)
@@ -124,7 +126,13 @@ def main(argv=None):
     log = lambda s: print(s, flush=True)
     from .build import source_hash
     report = {"source_hash": source_hash()}
-    if not args.skip_c2:
+    if args.resume:
+        with open(args.resume) as fh:
+            prev = json.load(fh)
+        if prev.get("source_hash") != report["source_hash"]:
+            raise SystemExit(f"{args.resume} was measured on other sources")
+        report = prev
+    if not args.skip_c2 and "c2" not in report:
         runs, tags = c2_runs()
         tw = twin(runs, args.c2_steps, 2000, export_u_at=(args.c2_steps,), log=log, precisions=precs)
         report["c2"] = dict(runs=tags, steps=args.c2_steps, compare=compare(tw, len(runs)),
@@ -132,12 +140,15 @@ def main(argv=None):
         for row in report["c2"]["compare"]:
             log(f"c2 {row['precision']} run {row['run']}: max|dD| {row['max_dD']:.2e} "
                 f"max|dtheta| {row['max_dtheta']:.2e} u rel L2 {row['u_rel_l2']}")
-    report["c3"] = []
+    report.setdefault("c3", [])
+    done = {(r.get("lambda"), r["steps"]) for r in report["c3"]}
     ck = tuple(range(10000, args.c3_steps + 1, 10000)) or (args.c3_steps,)
     for lam in (float(v) for v in args.c3_lambdas.split(",") if v):
+        if (lam, args.c3_steps) in done:
+            continue
         p3, tag3 = c3_run(lam)
         tw3 = twin([p3], args.c3_steps, 2000, export_u_at=ck, log=log, precisions=precs)
-        rep = dict(run=tag3, steps=args.c3_steps, compare=compare(tw3, 1),
+        rep = dict(run=tag3, **{"lambda": lam}, steps=args.c3_steps, compare=compare(tw3, 1),
                    seconds={p: tw3[p]["seconds"] for p in precs})
         report["c3"].append(rep)
         for row in rep["compare"]:

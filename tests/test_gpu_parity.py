@@ -125,7 +125,7 @@ def test_launch_shapes_bit_identical(lbm):
     ref = None
     for shape in [dict(bx=16, by=8, bz=1), dict(bx=8, by=16, bz=3),
                   dict(bx=16, by=8, bz=8, persistent=64), dict(bx=8, by=16, bz=32),
-                  dict(bx=16, by=8, bz=5, persistent=8)]:
+                  dict(bx=16, by=8, bz=5, persistent=8), dict(bx=16, by=8, bz=0)]:
         s = lbm.Solver(d, "fp64")
         s.set_launch(**shape)
         s.step(25)
@@ -266,9 +266,13 @@ UNEVEN_STEPS = [300, 170, 250, 90]
 def test_uneven_batch_matches_oracle(lbm):
     """Four runs of different boxes, phases and parameters in one FP64
     batch, each given its own step count: every run's fields against the
-    oracle (the batched tile table, per-run parameters and masking)."""
+    oracle (the batched tile table, per-run parameters and masking, tiles of
+    each run's own height)."""
     futs = [oracle_pool.submit(d, n) for d, n in zip(UNEVEN_BATCH, UNEVEN_STEPS)]
     b = lbm.Batch(UNEVEN_BATCH, "fp64")
+    # tiles spanning each run's whole height (different per run), taken in
+    # turn by a persistent grid of 16 workgroups
+    b.set_launch(bx=16, by=8, bz=0, persistent=16)
     b.step(UNEVEN_STEPS)
     obs = b.observe()
     for r, fut in enumerate(futs):
