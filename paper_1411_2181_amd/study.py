@@ -110,12 +110,14 @@ def window(q):
     return CA_LO, sweep.ca_max(q["R"], q["c"], q["lam"], q["De"], q["fraction"])
 
 
-def single_runner(precision: str, log=None):
-    """One run at a time (no batching): the plain reference path."""
+def single_runner(precision: str, log=None, extend_to: int = 0):
+    """One run at a time (no batching): the plain reference path (with the
+    batched searches' horizon extension)."""
     def run(specs):
         out, total = [], 0.0
         for sp in specs:
-            res, sec = sweep.simulate([sp], precision, t_end=T_END, every=EVERY, progress=log)
+            res, sec = sweep.simulate([sp], precision, t_end=T_END, every=EVERY, progress=log,
+                                      extend_to=extend_to)
             total += sec
             r = res[0]
             out.append((r.broken, r.status, r.steps * r.params["nx"] * r.params["ny"] * r.params["nz"]))
@@ -187,10 +189,20 @@ def cmd_search(args, log):
     D = np.array([r["D"] for r in ok])
     TH = np.array([r["theta"] for r in ok])
     BR = np.array([r["broken"] for r in ok], dtype=float)
-    rng = np.random.default_rng(0)
-    perm = rng.permutation(len(ok))
-    nte = max(1, len(ok) // 10)
-    te, tr = perm[:nte], perm[nte:]
+    if args.holdout:
+        # a separate set of runs (another slice of the sampler), never trained on
+        hold = [r for r in load_data(args.holdout.split(","))["rows"] if r["status"] == 0]
+        n0 = len(ok)
+        X = np.concatenate([X, np.array([r["inputs"] for r in hold])])
+        D = np.concatenate([D, np.array([r["D"] for r in hold])])
+        TH = np.concatenate([TH, np.array([r["theta"] for r in hold])])
+        BR = np.concatenate([BR, np.array([r["broken"] for r in hold], dtype=float)])
+        tr, te = np.arange(n0), np.arange(n0, n0 + len(hold))
+    else:
+        rng = np.random.default_rng(0)
+        perm = rng.permutation(len(ok))
+        nte = max(1, len(ok) // 10)
+        te, tr = perm[:nte], perm[nte:]
 
     # train on the GPU with the project's kernels
     sg = Surrogate(batch_max=max(4096, len(ok)), seed=1)
@@ -206,10 +218,12 @@ def cmd_search(args, log):
         mae_theta_deg=float(np.mean(np.abs(pT[unb] - TH[te][unb]))) if unb.any() else None,
         breakup_accuracy=float(np.mean((pB >= 0.5) == (BR[te] > 0.5))))
     log(json.dumps(report))
-    # refit on every usable row for the searches
+    # refit on every usable training row for the searches (the held-out set
+    # of --holdout stays out)
     sg.close()
     sg = Surrogate(batch_max=max(4096, len(ok)), seed=1)
-    sg.fit(X, D, TH, BR, epochs=args.epochs, lr=2e-3)
+    keep = tr if args.holdout else np.arange(len(ok))
+    sg.fit(X[keep], D[keep], TH[keep], BR[keep], epochs=args.epochs, lr=2e-3)
 
     qs = query_searches(args.queries)
     if args.only:
@@ -289,7 +303,7 @@ def cmd_search(args, log):
         lo, hi = window(q)
         s64 = [sweep.Search(q["De"], q["lam"], q["c"], q["R"], lo, hi, hard_lo=lo, hard_hi=hi,
                             L2=q["L2"], fraction=q["fraction"])]
-        s64, t, _ = sweep.bisect(s64, tol=TOL, run=single_runner("fp64", log))
+        s64, t, _ = sweep.bisect(s64, tol=TOL, run=single_runner("fp64", log, getattr(args, "extend_to", 0)))
         t64 += t
         n64 += 1
         runs64 += s64[0].runs
@@ -360,7 +374,7 @@ def cmd_fp64(args, log):
         lo, hi = window(q)
         s64 = [sweep.Search(q["De"], q["lam"], q["c"], q["R"], lo, hi, hard_lo=lo, hard_hi=hi,
                             L2=q["L2"], fraction=q["fraction"])]
-        s64, t, _ = sweep.bisect(s64, tol=TOL, run=single_runner("fp64", log))
+        s64, t, _ = sweep.bisect(s64, tol=TOL, run=single_runner("fp64", log, getattr(args, "extend_to", 0)))
         a = s64[0]
         total += t
         runs += a.runs
@@ -412,6 +426,56 @@ def cmd_scan(args, log):
     return 0
 
 
+# Matrix solvent relaxation time per mode in cmd_modes: Newtonian and
+# droplet-viscoelastic runs use the search window's; the matrix-viscoelastic
+# droplet (total viscosity of the matrix solvent + polymer, lambda = 1) needs
+# a lower matrix solvent tau so the droplet's tau stays in the calibrated
+# (Laplace-consistent) range.
+MODE_TAU_MATRIX = {"N": 1.5, "DV": 1.5, "MV": 0.98}
+
+
+def cmd_modes(args, log):
+    """Newtonian, droplet-viscoelastic and matrix-viscoelastic droplets at
+    the same Ca, confinement 2R/W and viscosity ratio (lambda = 1 in the
+    total viscosities, the paper's choice in Section 3), for each De of the
+    list: elongation histories L_p(t)/2R, break-up step and daughter sizes,
+    the counterpart of the paper's Fig. 4 (its Section 3 compares the three
+    at 2R/W = 0.78).  All runs advance as one batch, up to --t-end steps,
+    extended to --extend-to for runs still elongating."""
+    specs, tags = [], []
+    for ca in (float(v) for v in args.ca.split(",")):
+        specs.append(sweep.RunSpec(args.R, args.c, ca, 0.0, 1.0, args.L2, args.fraction, phase="N",
+                                   tau_matrix=MODE_TAU_MATRIX["N"]))
+        tags.append(dict(mode="N", Ca=ca, De=0.0))
+        for De in (float(v) for v in args.De.split(",")):
+            for mode in ("DV", "MV"):
+                specs.append(sweep.RunSpec(args.R, args.c, ca, De, 1.0, args.L2, args.fraction,
+                                           phase=mode, tau_matrix=MODE_TAU_MATRIX[mode]))
+                tags.append(dict(mode=mode, Ca=ca, De=De))
+    res, sec = sweep.simulate(specs, args.precision, t_end=args.t_end, every=args.every,
+                              progress=log, extend_to=args.extend_to)
+    rows = []
+    for t, r in zip(tags, res):
+        tem = r.info["tau_em"]
+        hist = [dict(step=h[0], t_over_tau_em=h[0] / tem, D=h[1], theta=h[2],
+                     Lp_over_2R=h[3] / (2 * args.R), pieces=h[4]) for h in r.history]
+        rows.append(dict(t, tau=list(r.params["tau"]), tau_P=list(r.params["tau_P"]),
+                         u_wall=r.params["u_wall"], tau_em=tem, broken=r.broken,
+                         step_break=r.step_break, status=r.status, steps=r.steps,
+                         t_break_over_tau_em=(r.step_break / tem) if r.broken else None,
+                         daughter_nodes=r.pieces,
+                         Lp_max_over_2R=max(h["Lp_over_2R"] for h in hist), history=hist))
+        log(f"{t['mode']:2s} Ca={t['Ca']:.3f} De={t['De']:.2f}: "
+            + (f"breaks at {r.step_break} into {len(r.pieces)} {r.pieces}" if r.broken else "stable")
+            + f", max Lp/2R {rows[-1]['Lp_max_over_2R']:.2f}")
+    out = dict(c=args.c, R=args.R, L2=args.L2, fraction=args.fraction, lam=1.0,
+               tau_matrix=MODE_TAU_MATRIX, precision=args.precision, t_end=args.t_end,
+               extend_to=args.extend_to, every=args.every, seconds=sec, rows=rows)
+    with open(args.out, "w") as fh:
+        json.dump(out, fh, indent=1, default=_plain)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -425,6 +489,8 @@ def main(argv=None):
     s.add_argument("out")
     s.add_argument("--data", required=True, help="comma-separated generate outputs")
     s.add_argument("--queries", type=int, default=32)
+    s.add_argument("--holdout", default="", help="generate outputs held out of training "
+                   "(scored only); without it 10 %% of --data is held out")
     s.add_argument("--epochs", type=int, default=3000)
     s.add_argument("--fp64-queries", type=int, default=1)
     s.add_argument("--precision", default="fp32", choices=["fp32", "fp16s"],
@@ -443,6 +509,8 @@ def main(argv=None):
     f64.add_argument("out")
     f64.add_argument("--queries", type=int, default=4)
     f64.add_argument("--compare", default="", help="a search output of the same query triples")
+    f64.add_argument("--extend-to", type=int, default=2 * T_END,
+                     help="horizon extension of runs still elongating (as in search); 0: off")
     k = sub.add_parser("scan")
     k.add_argument("out")
     k.add_argument("--De", type=float, required=True)
@@ -454,10 +522,22 @@ def main(argv=None):
     k.add_argument("--t-end", type=int, default=T_END)
     k.add_argument("--every", type=int, default=500)
     k.add_argument("--precision", default="fp32", choices=["fp32", "fp16s"])
+    m = sub.add_parser("modes")
+    m.add_argument("out")
+    m.add_argument("--c", type=float, default=0.78)
+    m.add_argument("--R", type=float, default=24.0)
+    m.add_argument("--ca", required=True, help="comma-separated capillary numbers")
+    m.add_argument("--De", default="0.2,2", help="comma-separated Deborah numbers")
+    m.add_argument("--fraction", type=float, default=0.4)
+    m.add_argument("--L2", type=float, default=100.0)
+    m.add_argument("--t-end", type=int, default=T_END)
+    m.add_argument("--extend-to", type=int, default=2 * T_END)
+    m.add_argument("--every", type=int, default=500)
+    m.add_argument("--precision", default="fp32", choices=["fp32", "fp16s"])
     args = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
     cmd = {"generate": cmd_generate, "search": cmd_search, "elongation": cmd_elongation,
-           "scan": cmd_scan, "fp64": cmd_fp64}
+           "scan": cmd_scan, "fp64": cmd_fp64, "modes": cmd_modes}
     return cmd[args.cmd](args, log)
 
 

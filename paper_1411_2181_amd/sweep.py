@@ -39,6 +39,7 @@ class RunSpec:
     L2: float = 100.0
     fraction: float = 0.4
     phase: str = "DV"
+    tau_matrix: float = 0.0    # matrix solvent relaxation time; 0: TAU_MATRIX
 
     def inputs(self):
         """Surrogate inputs: (Ca, De, lambda, 2R/W, L^2, polymer fraction)."""
@@ -97,7 +98,8 @@ def lattice(spec: RunSpec):
     nx, ny, nz = box(spec.R, spec.c)
     phase = spec.phase if spec.De > 0 else "N"
     p, info = physics.lattice_params(nx, ny, nz, spec.R, spec.Ca, spec.De, spec.lam, phase=phase,
-                                     L2=spec.L2, fraction=spec.fraction, tau_matrix=TAU_MATRIX,
+                                     L2=spec.L2, fraction=spec.fraction,
+                                     tau_matrix=spec.tau_matrix or TAU_MATRIX,
                                      u_max=U_MAX * (1 + 1e-9))
     return p, info
 

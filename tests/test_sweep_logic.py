@@ -239,3 +239,37 @@ def test_scan_report(monkeypatch, tmp_path):
     assert broken["broken"] and broken["step_break"] == 2000 and broken["daughter_nodes"] == [300, 300]
     assert broken["t_break_over_tau_em"] == pytest.approx(40.0)
     assert stable["Lp_max_over_2R"] == pytest.approx((48.0 + 4.0) / 48.0)
+
+
+def test_modes_report_maps_each_mode(monkeypatch, tmp_path):
+    """The Newtonian / droplet- / matrix-viscoelastic comparison builds one run
+    per mode, Ca and De with lambda = 1 and each mode's matrix solvent tau; the
+    lattice parameters of every run lie in the calibrated window."""
+    import json
+    import types
+    from paper_1411_2181_amd import physics, study
+
+    def fake_simulate(specs, precision, t_end=None, every=500, **kw):
+        out = []
+        for sp in specs:
+            p, info = sweep.lattice(sp)
+            r = sweep.RunResult(sp, p, info)
+            r.history = [(every, 0.1, 45.0, 2 * sp.R, 1)]
+            r.steps = every
+            out.append(r)
+        return out, 1.0
+    monkeypatch.setattr(sweep, "simulate", fake_simulate)
+    out = tmp_path / "modes.json"
+    args = types.SimpleNamespace(out=str(out), c=0.78, R=24.0, ca="0.16,0.24", De="0.2,2",
+                                 fraction=0.4, L2=100.0, t_end=1000, extend_to=0, every=500,
+                                 precision="fp32")
+    study.cmd_modes(args, lambda m: None)
+    d = json.loads(out.read_text())
+    rows = d["rows"]
+    assert [r["mode"] for r in rows[:5]] == ["N", "DV", "MV", "DV", "MV"] and len(rows) == 10
+    for r in rows:
+        tA, tB = r["tau"]
+        physics.sigma_for(tA, tB)                  # raises outside the calibrated window
+        assert r["u_wall"] <= sweep.U_MAX * (1 + 1e-9)
+        assert tB == pytest.approx(study.MODE_TAU_MATRIX[r["mode"]])   # the matrix is B
+        assert r["Lp_max_over_2R"] == pytest.approx(1.0)
