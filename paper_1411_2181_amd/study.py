@@ -243,6 +243,11 @@ def cmd_search(args, log):
     run_plain = sweep.lattice_runner(prec, log=log, t_end=T_END, every=EVERY, **ext)
     plain, t_plain, r_plain = sweep.bisect(plain_searches(), tol=TOL, run=run_plain)
     log(f"plain bisection ({prec}): {t_plain:.1f} s, {r_plain} rounds, {sum(s.runs for s in plain)} runs")
+    # the plain search's brackets so far (the file is rewritten with the whole report at the end)
+    with open(args.out, "w") as fh:
+        json.dump(dict(report, partial=dict(plain_seconds=t_plain, plain_rounds=r_plain, rows=[
+            dict(q, plain=dict(ca_cr=a.ca_cr, bracket=[a.lo, a.hi], outside=a.outside, runs=a.runs))
+            for q, a in zip(qs, plain)])), fh, indent=1, default=_plain)
 
     # surrogate-proposed brackets, batched FP32
     prop, proposals = [], []
@@ -388,10 +393,12 @@ def cmd_fp64(args, log):
         log(f"fp64 single: query {k + 1} {t:.1f} s, {a.runs} runs, Ca_cr {a.ca_cr:.3f} "
             f"({a.outside or 'inside'})" + (f", same bracket as batched: {row['same_bracket']}"
                                               if ref is not None else ""))
-    out = dict(queries=len(qs), tol=TOL, t_end=T_END, seconds=total, runs=runs,
-               sweeps_per_hour=len(qs) / total * 3600, rows=rows)
-    with open(args.out, "w") as fh:
-        json.dump(out, fh, indent=1, default=_plain)
+        # the report so far after every query (a long run keeps what it finished)
+        out = dict(queries=len(rows), tol=TOL, t_end=T_END,
+                   extend_to=getattr(args, "extend_to", 0), seconds=total, runs=runs,
+                   sweeps_per_hour=len(rows) / total * 3600, rows=rows)
+        with open(args.out, "w") as fh:
+            json.dump(out, fh, indent=1, default=_plain)
     log(f"fp64 single: {len(qs)} queries, {total:.1f} s, {runs} runs, "
         f"{out['sweeps_per_hour']:.1f} sweeps per hour")
     return 0
