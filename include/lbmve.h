@@ -106,6 +106,13 @@ typedef struct {
                             x_p the mass fraction of the polymer phase's
                             component; both 0 => mean-field coexistence
                             fractions at (G, rho_major + rho_minor)          */
+  uint64_t seed;         /* seed of the optional initial density noise       */
+  double init_noise;     /* its relative amplitude a, 0 <= a < 0.1 (0: none):
+                            component s's initial density at node n (x
+                            fastest) is rho (1 + a u), u = (w >> 11) 2^-52 - 1
+                            in [-1, 1) with w the SplitMix64 word of counter
+                            2 n + s: mix(seed + (2 n + s + 1) 0x9e3779b97f4a7c15)
+                            (Steele, Lea and Flood 2014, its finaliser)      */
 } lbm_params;
 
 /* Observables of one run at the current state. */

@@ -96,6 +96,32 @@ class Params:
             if lo is None:
                 lo, hi = self.rho_minor / rt, self.rho_major / rt
         self.chi_lo, self.chi_hi = lo, hi
+        self.seed = int(d.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
+        self.init_noise = float(d.get("init_noise", 0.0))
+
+
+def splitmix64(seed: int, k):
+    """Words k (uint64 array) of SplitMix64 with the given seed (Steele, Lea
+    and Flood, OOPSLA 2014): the finaliser applied to seed + (k + 1) * gamma,
+    gamma = 0x9e3779b97f4a7c15, all modulo 2^64."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (np.asarray(k, dtype=np.uint64) + np.uint64(1)) * np.uint64(0x9e3779b97f4a7c15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xbf58476d1ce4e5b9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94d049bb133111eb)
+        return z ^ (z >> np.uint64(31))
+
+
+def init_noise_factors(p):
+    """1 + a u per component and node (shape (2, nz, ny, nx)), u in [-1, 1)
+    from word 2 n + s of SplitMix64 (n the node index, x fastest): the
+    optional seeded perturbation of the initial densities."""
+    n = np.arange(p.nx * p.ny * p.nz, dtype=np.uint64).reshape(p.nz, p.ny, p.nx)
+    out = np.empty((2, p.nz, p.ny, p.nx))
+    for s in (0, 1):
+        w = splitmix64(p.seed, np.uint64(2) * n + np.uint64(s))
+        u = (w >> np.uint64(11)).astype(np.float64) * 2.0 ** -52 - 1.0
+        out[s] = 1.0 + p.init_noise * u
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -333,6 +359,9 @@ class Oracle:
                       < p.radius ** 2)
             rhoA = np.where(inside, p.rho_major, p.rho_minor)
             rhoB = np.where(inside, p.rho_minor, p.rho_major)
+            if p.init_noise > 0.0:
+                fac = init_noise_factors(p)
+                rhoA, rhoB = rhoA * fac[0], rhoB * fac[1]
             f = np.empty((2, Q) + shape)
             for i in range(Q):
                 f[0, i] = W[i] * rhoA

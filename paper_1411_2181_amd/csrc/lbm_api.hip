@@ -103,7 +103,7 @@ Layout make_layout(const lbm_params* p, int32_t nruns) {
   L.partials = take((size_t)nruns * lbm::AUX_BLOCKS * lbm::NOBS * 8);
   L.obs = take((size_t)nruns * lbm::NOBS * 8);
   L.rc = take((size_t)nruns * 4 * 8);
-  L.rinit = take((size_t)nruns * 2 * 8);
+  L.rinit = take((size_t)nruns * 4 * 8);
   L.total = off;
   return L;
 }
@@ -223,6 +223,7 @@ int validate(const lbm_params* p) {
     }
   }
   if (p->eta_P[0] > 0.0 && p->eta_P[1] > 0.0) return LBM_EINVAL;
+  if (!(p->init_noise >= 0.0 && p->init_noise < 0.1)) return LBM_EINVAL;
   if (!(p->chi_lo == 0.0 && p->chi_hi == 0.0)) {
     if (!(p->chi_hi > p->chi_lo) || !std::isfinite(p->chi_lo) || !std::isfinite(p->chi_hi))
       return LBM_EINVAL;
@@ -491,7 +492,7 @@ int lbm_batch_init(const lbm_params* runs, int32_t nruns, void* ws, size_t bytes
   c->prm.assign(runs, runs + nruns);
   c->done.assign(nruns, 0);
   int64_t off = 0;
-  std::vector<double> rc(4 * nruns), rinit(2 * nruns);
+  std::vector<double> rc(4 * nruns), rinit(4 * nruns);
   for (int r = 0; r < nruns; ++r) {
     c->runs.push_back(make_run(runs[r], off));
     off += c->runs.back().ld;
@@ -501,8 +502,10 @@ int lbm_batch_init(const lbm_params* runs, int32_t nruns, void* ws, size_t bytes
     rc[4 * r + 1] = centre ? 0.5 * (p.nx - 1) : p.cx;
     rc[4 * r + 2] = centre ? 0.5 * (p.ny - 1) : p.cy;
     rc[4 * r + 3] = centre ? 0.5 * (p.nz - 1) : p.cz;
-    rinit[2 * r] = p.rho_major;
-    rinit[2 * r + 1] = p.rho_minor;
+    rinit[4 * r] = p.rho_major;
+    rinit[4 * r + 1] = p.rho_minor;
+    rinit[4 * r + 2] = p.init_noise;
+    std::memcpy(&rinit[4 * r + 3], &p.seed, 8);   // the seed's bits
   }
   auto fail = [&](int code) { lbm_destroy(c); return code; };
   if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(LBM_EHIP);

@@ -29,7 +29,9 @@ __global__ void k_init(AuxArgs<T, S> a) {
   node_range(R.n, beg, end);
   const double rad = a.radius_centre[4 * r], cx = a.radius_centre[4 * r + 1];
   const double cy = a.radius_centre[4 * r + 2], cz = a.radius_centre[4 * r + 3];
-  const double rmaj = a.rho_init[2 * r], rmin = a.rho_init[2 * r + 1];
+  const double rmaj = a.rho_init[4 * r], rmin = a.rho_init[4 * r + 1];
+  const double noise = a.rho_init[4 * r + 2];
+  const uint64_t seed = __builtin_bit_cast(uint64_t, a.rho_init[4 * r + 3]);
   using St = Store<T, S>;
   S* f = a.P.f[0] + 38 * R.off;
   T* rho = a.P.rho[0] + 2 * R.off;
@@ -41,7 +43,17 @@ __global__ void k_init(AuxArgs<T, S> a) {
     const int z = (int)(n / ((int64_t)R.nx * R.ny));
     const double dx = x - cx, dy = y - cy, dz = z - cz;
     const bool inside = dx * dx + dy * dy + dz * dz < rad * rad;
-    const double rho_s[2] = {inside ? rmaj : rmin, inside ? rmin : rmaj};
+    double rho_s[2] = {inside ? rmaj : rmin, inside ? rmin : rmaj};
+    if (noise > 0.0) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        // u in [-1, 1) from the SplitMix64 word of counter 2n + s
+        const uint64_t w = splitmix64_mix(seed + (uint64_t)(2 * n + s + 1) * 0x9e3779b97f4a7c15ull);
+        const double u = (double)(w >> 11) * 0x1p-52 - 1.0;
+        const double t = noise * u;   // separate statements: no fused multiply-add
+        rho_s[s] = rho_s[s] * (1.0 + t);
+      }
+    }
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       rho[s * N + n] = T(rho_s[s]);

@@ -92,6 +92,15 @@ struct Store;
 #define LBM_NT_STORES 1
 #endif
 
+// SplitMix64's output function (G. Steele, D. Lea, C. Flood, "Fast splittable
+// pseudorandom number generators", OOPSLA 2014): the word of counter k of
+// seed s is splitmix64_mix(s + (k + 1) * 0x9e3779b97f4a7c15).
+__host__ __device__ inline uint64_t splitmix64_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
 // MurmurHash3's 32-bit finaliser (A. Appleby, public domain): a bijective
 // mixer, used as a counter-based generator.
 __device__ __forceinline__ uint32_t fmix32(uint32_t h) {

@@ -50,7 +50,7 @@ struct AuxArgs {
   int32_t* ncomp;          // per run: pieces counted
   int32_t* pieces;         // [nruns][MAX_PIECES]: node counts of counted pieces, unordered
   const double* radius_centre;  // [nruns][4]: R, cx, cy, cz  (init only)
-  const double* rho_init;       // [nruns][2]: rho_major, rho_minor (init only)
+  const double* rho_init;       // [nruns][4]: rho_major, rho_minor, init_noise, seed bits (init only)
 };
 
 // One time step over the tile table: grid.x workgroups (two per tile slot,

@@ -42,6 +42,7 @@ class LbmParams(ctypes.Structure):
         ("eta_P", ctypes.c_double * 2),
         ("L2", ctypes.c_double * 2),
         ("chi_lo", ctypes.c_double), ("chi_hi", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("init_noise", ctypes.c_double),
     ]
 
 
@@ -175,6 +176,8 @@ def make_params(d: dict, precision: str = "fp64") -> LbmParams:
         arr[0], arr[1] = float(v[0]), float(v[1])
     p.chi_lo = float(d.get("chi_lo", 0.0))
     p.chi_hi = float(d.get("chi_hi", 0.0))
+    p.seed = int(d.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
+    p.init_noise = float(d.get("init_noise", 0.0))
     return p
 
 

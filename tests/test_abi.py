@@ -131,3 +131,13 @@ def test_null_arguments_rejected(L):
     out = ctypes.c_void_p()
     # no workspace -> rejected before any device call
     assert L.lbm_init(ctypes.byref(p), None, 0, None, ctypes.byref(out)) == lbmve.LBM_EINVAL
+
+
+def test_init_noise_amplitude_is_validated(L):
+    """The seeded initial density noise takes a relative amplitude in [0, 0.1)."""
+    from paper_1411_2181_amd import lbmve
+    d = WL.small_droplet_viscoelastic()
+    for a, ok in ((0.0, True), (0.01, True), (0.099, True), (0.1, False), (-0.01, False),
+                  (float("nan"), False)):
+        p = lbmve.make_params(dict(d, seed=2**64 - 1, init_noise=a), "fp64")
+        assert (L.lbm_validate(ctypes.byref(p)) == 0) == ok, a

@@ -62,6 +62,31 @@ def test_init_state_exact(lbm):
     s.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_init_state_with_seeded_noise(lbm, precision):
+    """The optional initial density noise (seed, relative amplitude 1 %) is
+    the oracle's, word for word of the counter-based generator: FP64 fields
+    bit-exact, FP32 to its rounding; 100 steps later still at the bar."""
+    d = dict(WL.small_droplet_viscoelastic(), seed=987654321, init_noise=0.01)
+    s = lbm.Solver(d, precision)
+    o = Oracle(d)
+    rho = s.export("rho")
+    ref = np.stack([o.f[0].sum(axis=0), o.f[1].sum(axis=0)])
+    print(f"case seeded noise {precision}: rho spread {rho[0].std():.2e}", flush=True)
+    if precision == "fp64":
+        assert np.array_equal(s.export("f"), o.f) and np.array_equal(rho, ref)
+    else:
+        assert rel(rho, ref) <= 1e-7
+    # the noise is there, within its amplitude
+    rel0 = np.abs(rho / np.stack([Oracle(dict(d, init_noise=0.0)).f[c].sum(axis=0)
+                                  for c in (0, 1)]) - 1.0)
+    assert 0.009 < rel0.max() <= 0.01 + 1e-6
+    s.step(100)
+    o.step(100)
+    assert rel(s.export("f"), o.f) <= (1e-10 if precision == "fp64" else 1e-5)
+    s.close()
+
+
 @pytest.mark.parametrize("shape_xyz", [(17, 9, 12), (33, 5, 40)])
 @pytest.mark.parametrize("visc", ["none", "A", "B"])
 def test_random_state_ragged_parity(lbm, shape_xyz, visc):

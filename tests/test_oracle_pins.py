@@ -270,3 +270,26 @@ def test_fene_p_upwind_advection_of_a_step():
     Cn = fene_p_update(C, u, prm, u_p=up)
     want = c - (-0.5) * (np.roll(c, -1) - c)
     assert np.allclose(Cn[0, 1, 1], want, rtol=0, atol=1e-15)
+
+
+def test_splitmix64_published_words():
+    """The initial-noise generator is SplitMix64 (Steele, Lea and Flood 2014):
+    its first five words for seed 0 are the published ones, and the noise
+    factors are 1 + a u with u uniform in [-1, 1)."""
+    import numpy as np
+    from oracle.solver import Params, init_noise_factors, splitmix64
+    import workloads as WL
+    w = splitmix64(0, np.arange(5))
+    assert [int(v) for v in w] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F,
+                                   0xF88BB8A8724C81EC, 0x1B39896A51A8749B]
+    d = dict(WL.base_params(nx=40, ny=30, nz=20, radius=5.0), seed=2024, init_noise=0.01)
+    fac = init_noise_factors(Params(d))
+    u = (fac - 1.0) / 0.01
+    assert u.min() >= -1.0 and u.max() < 1.0
+    assert abs(u.mean()) < 0.02 and abs(u.var() - 1.0 / 3.0) < 0.02
+    # the two components draw different words; another seed, another field
+    assert not np.array_equal(fac[0], fac[1])
+    d2 = dict(d, seed=2025)
+    assert not np.array_equal(init_noise_factors(Params(d2)), fac)
+    # no noise: every factor is exactly one
+    assert np.all(init_noise_factors(Params(dict(d, init_noise=0.0))) == 1.0)
