@@ -75,7 +75,9 @@ int64_t max_tiles(const lbm_params* p, int32_t nruns) {
   // bound for every tile shape: bx >= 8, by >= 8, bz >= 1
   int64_t t = 0;
   for (int r = 0; r < nruns; ++r) t += (int64_t)((p[r].nx + 7) / 8) * ((p[r].ny + 7) / 8) * p[r].nz;
-  return (t + 7) / 8 * 8;
+  // tiles have at least 128 columns (half the bound) and each round of the
+  // table may add up to 7 padding entries: twice the tile count covers both
+  return (t + 7) / 8 * 8 + 64;
 }
 
 Layout make_layout(const lbm_params* p, int32_t nruns) {
@@ -121,6 +123,7 @@ struct lbm_ctx {
   Layout L{};
   lbm_launch launch{16, 8, 16, 0, 0};
   int64_t ntiles = 0;          // entries of the (XCD-permuted) tile table
+  int32_t n_cu = 256;          // compute units of the device
   std::map<int, hipGraphExec_t> graphs;
   std::map<int, hipGraph_t> graph_src;
 
@@ -294,9 +297,13 @@ void destroy_graphs(lbm_ctx* c) {
   c->graph_src.clear();
 }
 
-// Tile table: canonical order (run, tz, ty, tx), then permuted so that the
-// workgroups one XCD receives (dispatch is round-robin over the 8 XCDs) own a
-// contiguous block of tiles and share halo rows in that XCD's L2.
+// Tile table: canonical order (run, tz, ty, tx), cut into rounds of the
+// workgroups the GPU holds at once (a persistent grid's size, else CUs x
+// workgroups per CU); within a round the workgroups one XCD receives
+// (dispatch is round-robin over the 8 XCDs) own a contiguous block of tiles.
+// A round then covers one contiguous stretch of the lattice: the halo rows
+// between XCD blocks are read by both at about the same time, and only the
+// rows where one round meets the next are read at different times.
 int build_tiles(lbm_ctx* c) {
   const lbm_launch& l = c->launch;
   std::vector<Tile> canon;
@@ -309,14 +316,35 @@ int build_tiles(lbm_ctx* c) {
           canon.push_back(Tile{r, x, y, z, std::min(z + bzr, R.nz)});
   }
   const int64_t T = (int64_t)canon.size();
-  const int64_t Tp = (T + 7) / 8 * 8;
-  if (Tp > c->L.tiles_cap) return LBM_EINVAL;
-  std::vector<Tile> table(Tp);
-  const int64_t per = Tp / 8;
-  for (int64_t p = 0; p < Tp; ++p) {
-    const int64_t cidx = (p % 8) * per + p / 8;
-    table[p] = cidx < T ? canon[cidx] : Tile{-1, 0, 0, 0, 0};
+  int64_t cap = 0;   // workgroups resident at once
+  if (l.persistent > 0) {
+    cap = std::max(8, l.persistent / 8 * 8);
+  } else {
+    int per_cu = 0;
+    bool wide = l.grouped != 0;
+    for (const RunDev& R : c->runs)
+      wide |= (int64_t)lbm::Q * R.ld * (int64_t)(c->prec == LBM_FP64 ? 8 : c->prec == LBM_FP32 ? 4 : 2) >=
+              (int64_t)1 << 32;
+    by_precision(c->prec, [&](auto* tt, auto* ss) {
+      using T_ = std::remove_pointer_t<decltype(tt)>;
+      using S_ = std::remove_pointer_t<decltype(ss)>;
+      per_cu = lbm::step_blocks_per_cu<T_, S_>(l.bx, l.by, wide);
+    });
+    cap = (int64_t)std::max(1, per_cu) * c->n_cu / 8 * 8;
   }
+  cap = std::max<int64_t>(cap, 8);
+  std::vector<Tile> table;
+  table.reserve(T + 8 * (T / cap + 1));
+  for (int64_t r0 = 0; r0 < T; r0 += cap) {
+    const int64_t n = std::min(cap, T - r0);
+    const int64_t per = (n + 7) / 8;   // tiles per XCD in this round
+    for (int64_t p = 0; p < 8 * per; ++p) {
+      const int64_t cidx = (p % 8) * per + p / 8;
+      table.push_back(cidx < n ? canon[r0 + cidx] : Tile{-1, 0, 0, 0, 0});
+    }
+  }
+  const int64_t Tp = (int64_t)table.size();
+  if (Tp > c->L.tiles_cap) return LBM_EINVAL;
   HIPCHK(hipStreamSynchronize(c->stream));
   HIPCHK(hipMemcpy(c->at<Tile>(c->L.tiles), table.data(), Tp * sizeof(Tile), hipMemcpyHostToDevice));
   c->ntiles = Tp;
@@ -486,6 +514,7 @@ int lbm_batch_init(const lbm_params* runs, int32_t nruns, void* ws, size_t bytes
   if (!c) return LBM_EINVAL;
   c->nruns = nruns;
   c->prec = runs[0].precision;
+  c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   c->stream = (hipStream_t)stream;
   c->ws = (char*)ws;
   c->L = L;

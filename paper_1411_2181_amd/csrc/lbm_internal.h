@@ -61,6 +61,8 @@ void launch_step(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s);
 // compute type T (the FP64 instance has fewer: its LDS rings are twice as
 // large).
 bool step_shape_ok(int bx, int by, bool fp64);
+template <typename T, typename S>
+int step_blocks_per_cu(int bx, int by, bool wide);
 
 template <typename T, typename S>
 void launch_init(const AuxArgs<T, S>& a, hipStream_t s);

@@ -718,6 +718,25 @@ void launch_step(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s) 
 #undef STEP_CASE
 }
 
+// Workgroups of the step kernel that one CU holds at once (LDS, registers).
+template <typename T, typename S>
+int step_blocks_per_cu(int bx, int by, bool wide) {
+  int n = 0;
+  auto occ = [&](auto kern, int threads) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, threads, 0) != hipSuccess) n = 0;
+  };
+#define STEP_OCC(BX, BY)                                                            \
+  if (bx == BX && by == BY) {                                                       \
+    if constexpr (step_fits<BX, BY, T>()) {                                         \
+      if (wide) occ(k_step<T, S, BX, BY, DG_WIDE>, 2 * BX * BY);                     \
+      else occ(k_step<T, S, BX, BY, Q>, 2 * BX * BY);                                \
+    }                                                                               \
+  }
+  LBM_FOR_SHAPES(STEP_OCC)
+#undef STEP_OCC
+  return n;
+}
+
 template <typename T, typename S>
 void launch_flow(const AuxArgs<T, S>& a, hipStream_t s) {
   k_flow<T, S><<<dim3(AUX_BLOCKS, a.nruns), AUX_THREADS, 0, s>>>(a);
@@ -725,6 +744,7 @@ void launch_flow(const AuxArgs<T, S>& a, hipStream_t s) {
 
 #define LBM_INST(T, S)                                                                  \
   template void launch_step<T, S>(const StepArgs<T, S>&, dim3, dim3, hipStream_t);     \
+  template int step_blocks_per_cu<T, S>(int, int, bool);                                \
   template void launch_flow<T, S>(const AuxArgs<T, S>&, hipStream_t);
 LBM_INST(double, double)
 LBM_INST(float, float)
