@@ -514,6 +514,9 @@ int lbm_batch_init(const lbm_params* runs, int32_t nruns, void* ws, size_t bytes
   if (!c) return LBM_EINVAL;
   c->nruns = nruns;
   c->prec = runs[0].precision;
+  // default launch: whole-column tiles of the shape the autotuner picks for
+  // single lattices (32x8; 16x8 in FP64, whose rings are twice as large)
+  c->launch = c->prec == LBM_FP64 ? lbm_launch{16, 8, 0, 0, 0} : lbm_launch{32, 8, 0, 0, 0};
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   c->stream = (hipStream_t)stream;
   c->ws = (char*)ws;

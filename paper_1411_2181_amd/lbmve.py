@@ -284,7 +284,7 @@ class Batch:
         _check(lib().lbm_get_launch(self._c(), ctypes.byref(l)), "get_launch")
         return dict(bx=l.bx, by=l.by, bz=l.bz, persistent=l.persistent, grouped=l.grouped)
 
-    def set_launch(self, bx=16, by=8, bz=16, persistent=0, grouped=0):
+    def set_launch(self, bx=32, by=8, bz=0, persistent=0, grouped=0):
         l = LbmLaunch(bx, by, bz, persistent, grouped)
         _check(lib().lbm_set_launch(self._c(), ctypes.byref(l)), "set_launch")
 
