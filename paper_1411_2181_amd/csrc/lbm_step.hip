@@ -33,7 +33,10 @@
 //            collision reads, the node moments and the physical velocity.
 // The loads of the next plane's densities and C, of the populations of the
 // next plane to collide and of the momenta of plane r are in flight while
-// the rest of the iteration computes.
+// the rest of the iteration computes; the population loads and the moment
+// and C stores are spread over both phases (FP32, FP64).  The registers of
+// the iteration's global stores are held to its end, so that no store's
+// data is overwritten while it may still be read (a wait on the store).
 //
 // Storage and collision.  Populations are held as
 // g_i = f_i - w_i (rho + 3 c_i.j) against the moments of the node that holds
@@ -43,8 +46,9 @@
 //   f*_i(s) = (1 - w) g_i(s) + w_i [a + 3 c_i.P + b (c_i.u^eq)^2];
 // the arriving value is re-referenced to the moments of x, the new moments
 // of x are the old ones plus the sums of the re-referenced values, and the
-// value stored is the difference to the new moments.  Every rounding acts on
-// a small difference.
+// value stored is the difference to the new moments.  The records are read
+// from LDS one whole 16-byte vector at a time: lanes 16 bytes apart reading
+// fewer values would share LDS banks.
 //
 // The set-up (walls at -+U_w half a link outside z = 0 and z = nz-1, periodic
 // x and y) is Section 3.  A node's arithmetic does not depend on the tile
