@@ -20,6 +20,12 @@ Discrete readings (the paper defers the discretisation to its methods paper):
     by mass fraction.
   * Shan-Chen velocity-shift forcing: u' = sum_s(j_s/tau_s)/sum_s(rho_s/tau_s),
     u^eq_s = u' + tau_s F_s/rho_s; physical u = (sum_s j_s + sum_s F_s/2)/rho.
+  * Optional two-relaxation-time collision (a model variant beyond the
+    paper's BGK): the parts of f symmetric and antisymmetric under c -> -c
+    relax at 1/tau and 1/tau^-.  Momentum is the antisymmetric moment, so
+    the velocity shift takes tau^- wherever BGK has tau: the collision
+    changes j_s by (rho_s u^eq_s - j_s)/tau^-_s, which conserves the total
+    momentum up to the forces.  tau^- = tau is BGK.
   * FENE-P by explicit Euler with dt = 1: centred grad u, first-order upwind
     advection; C^{n+1} uses u^n and C^n; F^P uses C^n.
   * Ghosts: rho mirror in z, C zero-gradient in z, u extrapolated linearly
@@ -98,6 +104,12 @@ class Params:
         self.chi_lo, self.chi_hi = lo, hi
         self.seed = int(d.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
         self.init_noise = float(d.get("init_noise", 0.0))
+        # antisymmetric relaxation times (0 or absent: tau, i.e. BGK)
+        tm = d.get("tau_minus") or (0.0, 0.0)
+        self.tau_minus = tuple(float(t) if float(t) > 0.0 else self.tau[s]
+                               for s, t in enumerate(tm))
+        # uniform acceleration g, F_s += rho_s g (closed-form channel tests)
+        self.body_accel = tuple(float(v) for v in d.get("body_accel", (0.0, 0.0, 0.0)))
 
 
 def splitmix64(seed: int, k):
@@ -235,11 +247,16 @@ def polymer_force(T_p, shape):
 
 
 def forces(rho, C, prm: Params):
-    """Total force on each component, F_s = F^SC_s + (rho_s/rho) F^P."""
+    """Total force on each component, F_s = F^SC_s + (rho_s/rho) F^P
+    (+ rho_s g with the optional uniform acceleration g)."""
     rhoA, rhoB = rho[0], rho[1]
     shape = rhoA.shape
     rhoA_p, rhoB_p = pad_mirror_z(rhoA), pad_mirror_z(rhoB)
     FA, FB = shan_chen_force(rhoA_p, rhoB_p, rhoA, rhoB, prm.G)
+    if any(prm.body_accel):
+        g = np.array(prm.body_accel).reshape(3, 1, 1, 1)
+        FA = FA + rhoA * g
+        FB = FB + rhoB * g
     if prm.phase is not None:
         T_p = polymer_stress(pad_mirror_z(C), rhoA_p, rhoB_p, prm)
         FP = polymer_force(T_p, shape)
@@ -252,8 +269,9 @@ def forces(rho, C, prm: Params):
 def velocities(rho, j, FA, FB, prm: Params):
     """Shan-Chen common velocity u', per-component equilibrium velocities
     u^eq_s = u' + tau_s F_s/rho_s, and the physical velocity
-    u = (j_A + j_B + (F_A + F_B)/2)/rho."""
-    tA, tB = prm.tau
+    u = (j_A + j_B + (F_A + F_B)/2)/rho.  tau_s is the relaxation time of
+    the momentum: tau^-_s (equal to tau_s under BGK)."""
+    tA, tB = prm.tau_minus
     rhoA, rhoB = rho[0], rho[1]
     up = (j[0] / tA + j[1] / tB) / (rhoA / tA + rhoB / tB)
     ueqA = up + tA * FA / rhoA
@@ -263,12 +281,26 @@ def velocities(rho, j, FA, FB, prm: Params):
 
 
 def collide(f, rho, ueqA, ueqB, prm: Params):
-    """BGK: f*_si = f_si - (f_si - f^eq_i(rho_s, u^eq_s))/tau_s."""
+    """BGK: f*_si = f_si - (f_si - f^eq_i(rho_s, u^eq_s))/tau_s; a component
+    with tau^-_s != tau_s takes the two-relaxation-time collision."""
     out = np.empty_like(f)
     for s, ueq in ((0, ueqA), (1, ueqB)):
         feq = d3q19.equilibrium(rho[s], ueq)
-        out[s] = f[s] - (f[s] - feq) / prm.tau[s]
+        if prm.tau_minus[s] == prm.tau[s]:
+            out[s] = f[s] - (f[s] - feq) / prm.tau[s]
+        else:
+            out[s] = collide_trt(f[s], feq, prm.tau[s], prm.tau_minus[s])
     return out
+
+
+def collide_trt(f, feq, tau_plus, tau_minus):
+    """Two-relaxation-time collision of one component: with
+    f^+-_i = (f_i +- f_opp(i))/2 and the same split of f^eq,
+    f*_i = f_i - (f^+_i - f^eq+_i)/tau^+ - (f^-_i - f^eq-_i)/tau^-."""
+    fo, eo = f[OPP], feq[OPP]
+    fp, fm = 0.5 * (f + fo), 0.5 * (f - fo)
+    ep, em = 0.5 * (feq + eo), 0.5 * (feq - eo)
+    return f - (fp - ep) / tau_plus - (fm - em) / tau_minus
 
 
 def fene_p_update(C, u, prm: Params, u_p=None):

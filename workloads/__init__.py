@@ -19,6 +19,8 @@ Parameter dictionaries use the field names of ``lbm_params`` in
     G                     Shan-Chen coupling between the two components
     tau                   (tau_A, tau_B) BGK relaxation times; A is the droplet
                           component, B the matrix component
+    tau_minus             (tau^-_A, tau^-_B) antisymmetric relaxation times of
+                          the two-relaxation-time collision; 0 = tau (BGK)
     tau_P, eta_P, L2      per-phase FENE-P parameters (A, B); a phase is
                           viscoelastic when its eta_P > 0
     chi_lo, chi_hi        bounds of the polymer-phase indicator (0 = default)
@@ -44,6 +46,7 @@ _BASE = dict(
     tau=(1.0, 1.0),
     tau_P=(1.0, 1.0), eta_P=(0.0, 0.0), L2=(100.0, 100.0),
     chi_lo=0.0, chi_hi=0.0,
+    tau_minus=(0.0, 0.0),
 )
 
 
