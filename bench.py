@@ -92,12 +92,15 @@ def measured_traffic(precision, launch, box=BOX):
     return entry["launches"].get(f"{launch['bx']}x{launch['by']}x{launch['bz']}")
 
 
-def gpu_run(precision, steps, warmup, launch=None, box=BOX):
+def gpu_run(precision, steps, warmup, launch=None, box=BOX, tau_minus=None):
     """Autotune (unless ``launch`` pins the shape), then the graph-replayed
-    timed region, then ``steps`` eager steps with HIP events per pass."""
+    timed region, then ``steps`` eager steps with HIP events per pass.
+    ``tau_minus`` switches the collision to two relaxation times."""
     import torch
     from paper_1411_2181_amd import autotune, lbmve
     p, info = workload_params(*box)
+    if tau_minus:
+        p["tau_minus"] = tuple(tau_minus)
     s = lbmve.Solver(p, precision)
     if launch:
         s.set_launch(**launch)
@@ -121,7 +124,7 @@ def gpu_run(precision, steps, warmup, launch=None, box=BOX):
     s.close()
     wall = sorted(regions)[len(regions) // 2]
     return dict(nodes=nodes, wall=wall, regions=regions, ms=ms, obs=obs, params=p,
-                info=info, launch=launch, tuned=tuned, box=tuple(box))
+                info=info, launch=launch, tuned=tuned, box=tuple(box), trt=bool(tau_minus))
 
 
 def copy_bandwidth(gib=1, reps=5):
@@ -233,7 +236,8 @@ def roofline(precision, r):
     ms = r["ms"]
     balg = B_ALG[precision]
     ach = balg * nodes / (ms * 1e-3) / 1e9
-    tr = measured_traffic(precision, r["launch"], r.get("box", BOX))
+    # the committed counters are of the BGK kernel
+    tr = None if r.get("trt") else measured_traffic(precision, r["launch"], r.get("box", BOX))
     out = {
         "bound": "hbm",
         "kernel": "k_step (forces, collide-stream of both components, FENE-P: the whole step)",
@@ -267,8 +271,12 @@ def main():
     ap.add_argument("--box", default="512x256x128",
                     help="lattice NXxNYxNZ (default: the full case; 64x256x128 is one GPU's "
                          "x-slab of it in an 8-way decomposition)")
+    ap.add_argument("--tau-minus", default="",
+                    help="A,B: odd-moment relaxation times (two-relaxation-time collision "
+                         "instead of BGK; the throughput of that variant)")
     args = ap.parse_args()
     box = tuple(int(t) for t in args.box.lower().split("x"))
+    tau_minus = tuple(float(t) for t in args.tau_minus.split(",")) if args.tau_minus else None
     launch = None
     if args.launch:
         v = [int(t) for t in args.launch.lower().split("x")]
@@ -283,7 +291,7 @@ def main():
         pmc_pass(args.precision, launch=launch)
         return
 
-    r = gpu_run(args.precision, args.steps, args.warmup, launch, box)
+    r = gpu_run(args.precision, args.steps, args.warmup, launch, box, tau_minus)
     nodes, wall = r["nodes"], r["wall"]
     mlups = nodes * args.steps / wall / 1e6
     out = {
@@ -312,12 +320,13 @@ def main():
             "tau": [round(t, 5) for t in r["params"]["tau"]],
             "tau_P": round(r["params"]["tau_P"][1], 2),
             "launch": r["launch"],
+            "collision": f"TRT tau_minus={list(tau_minus)}" if tau_minus else "BGK",
         },
         "roofline": roofline(args.precision, r),
     }
     variants = [v for v in args.variants.split(",") if v and v != args.precision]
     for v in variants:
-        rv = gpu_run(v, args.steps, args.warmup, box=box)
+        rv = gpu_run(v, args.steps, args.warmup, box=box, tau_minus=tau_minus)
         mv = rv["nodes"] * args.steps / rv["wall"] / 1e6
         out[f"variant_{v}"] = {"value": round(mv, 1), "unit": "MLUPS",
                                "ms_per_step": round(rv["wall"] / args.steps * 1e3, 4),

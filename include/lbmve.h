@@ -96,7 +96,9 @@ typedef struct {
   double rho_major;      /* majority density of each component (> 0)         */
   double rho_minor;      /* minority density (> 0)                            */
   double G;              /* Shan-Chen coupling (>= 0)                         */
-  double tau[2];         /* BGK relaxation time of A and B, > 0.5            */
+  double tau[2];         /* relaxation time of A and B, > 0.5: BGK, or the
+                            rate of the parts of f even under c -> -c (it
+                            sets the viscosity) when tau_minus is given     */
   double tau_P[2];       /* polymer relaxation time of phase A, B (> 0)      */
   double eta_P[2];       /* polymer viscosity of phase A, B; a phase is
                             viscoelastic iff eta_P > 0; at most one may be   */
@@ -113,6 +115,15 @@ typedef struct {
                             in [-1, 1) with w the SplitMix64 word of counter
                             2 n + s: mix(seed + (2 n + s + 1) 0x9e3779b97f4a7c15)
                             (Steele, Lea and Flood 2014, its finaliser)      */
+  double tau_minus[2];   /* two-relaxation-time collision (a model variant
+                            beyond the paper's BGK): relaxation time of the
+                            parts of f odd under c -> -c for A and B, > 0.5;
+                            0 selects tau (BGK).  The odd parts carry the
+                            momentum, so the velocity shift of the forcing
+                            takes tau_minus where BGK takes tau.  With
+                            Lambda = (tau - 1/2)(tau_minus - 1/2) = 3/16 the
+                            half-way bounce-back walls hold a force-driven
+                            channel parabola exactly                        */
 } lbm_params;
 
 /* Observables of one run at the current state. */

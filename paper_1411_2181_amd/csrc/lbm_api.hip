@@ -157,8 +157,10 @@ lbm::StepArgs<T, S> step_args(const lbm_ctx* c) {
   a.gstep = c->at<int32_t>(c->L.gstep);
   a.any_visc = 0;
   a.wide = c->launch.grouped;
+  a.trt = 0;
   for (const RunDev& R : c->runs) {
     a.any_visc |= R.visc >= 0;
+    a.trt |= R.tau_m[0] != R.tau[0] || R.tau_m[1] != R.tau[1];
     a.wide |= (int64_t)lbm::Q * R.ld * (int64_t)sizeof(S) >= (int64_t)1 << 32;
   }
   return a;
@@ -219,6 +221,8 @@ int validate(const lbm_params* p) {
   if (!(p->G >= 0.0) || !std::isfinite(p->G)) return LBM_EINVAL;
   for (int s = 0; s < 2; ++s) {
     if (!(p->tau[s] > 0.5) || !std::isfinite(p->tau[s])) return LBM_EINVAL;
+    if (p->tau_minus[s] != 0.0 && (!(p->tau_minus[s] > 0.5) || !std::isfinite(p->tau_minus[s])))
+      return LBM_EINVAL;
     if (!(p->eta_P[s] >= 0.0) || !std::isfinite(p->eta_P[s])) return LBM_EINVAL;
     if (p->eta_P[s] > 0.0) {
       if (!(p->tau_P[s] > 0.0) || !std::isfinite(p->tau_P[s])) return LBM_EINVAL;
@@ -259,6 +263,8 @@ RunDev make_run(const lbm_params& p, int64_t off) {
   for (int s = 0; s < 2; ++s) {
     R.tau[s] = p.tau[s];
     R.inv_tau[s] = 1.0 / p.tau[s];
+    R.tau_m[s] = p.tau_minus[s] != 0.0 ? p.tau_minus[s] : p.tau[s];
+    R.inv_tau_m[s] = 1.0 / R.tau_m[s];
   }
   if (R.visc >= 0) {
     const int v = R.visc;
@@ -321,14 +327,16 @@ int build_tiles(lbm_ctx* c) {
     cap = std::max(8, l.persistent / 8 * 8);
   } else {
     int per_cu = 0;
-    bool wide = l.grouped != 0;
-    for (const RunDev& R : c->runs)
+    bool wide = l.grouped != 0, trt = false;
+    for (const RunDev& R : c->runs) {
       wide |= (int64_t)lbm::Q * R.ld * (int64_t)(c->prec == LBM_FP64 ? 8 : c->prec == LBM_FP32 ? 4 : 2) >=
               (int64_t)1 << 32;
+      trt |= R.tau_m[0] != R.tau[0] || R.tau_m[1] != R.tau[1];
+    }
     by_precision(c->prec, [&](auto* tt, auto* ss) {
       using T_ = std::remove_pointer_t<decltype(tt)>;
       using S_ = std::remove_pointer_t<decltype(ss)>;
-      per_cu = lbm::step_blocks_per_cu<T_, S_>(l.bx, l.by, wide);
+      per_cu = lbm::step_blocks_per_cu<T_, S_>(l.bx, l.by, wide, trt);
     });
     cap = (int64_t)std::max(1, per_cu) * c->n_cu / 8 * 8;
   }

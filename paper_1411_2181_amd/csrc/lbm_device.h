@@ -60,9 +60,10 @@ struct RunDev {
   int32_t min_cc;             // smallest droplet piece counted (nodes)
   int32_t pad0;
   double u_wall, G;
-  double tau[2], inv_tau[2];
+  double tau[2], inv_tau[2];          // even (viscous) rate: BGK tau, or TRT tau^+
   double inv_tauP, etaP_over_tauP, L2;
   double chi_lo, inv_chi_range;
+  double tau_m[2], inv_tau_m[2];      // odd (momentum) rate: tau^- (= tau under BGK)
 };
 
 // One tile of the step launch: a bx*by column block at (x0, y0) covering

@@ -15,6 +15,7 @@ struct StepArgs {
   const int32_t* gstep;   // step index within the current step call
   int32_t any_visc;       // some run of the batch carries a polymer phase
   int32_t wide;           // some run's 19 population arrays span >= 4 GiB
+  int32_t trt;            // some run has tau^- != tau (two-relaxation-time)
 };
 
 // Population addressing of the step kernel: direction i of a run is read
@@ -62,7 +63,7 @@ void launch_step(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s);
 // large).
 bool step_shape_ok(int bx, int by, bool fp64);
 template <typename T, typename S>
-int step_blocks_per_cu(int bx, int by, bool wide);
+int step_blocks_per_cu(int bx, int by, bool wide, bool trt);
 
 template <typename T, typename S>
 void launch_init(const AuxArgs<T, S>& a, hipStream_t s);

@@ -46,7 +46,12 @@
 //   f*_i(s) = (1 - w) g_i(s) + w_i [a + 3 c_i.P + b (c_i.u^eq)^2];
 // the arriving value is re-referenced to the moments of x, the new moments
 // of x are the old ones plus the sums of the re-referenced values, and the
-// value stored is the difference to the new moments.  The records are read
+// value stored is the difference to the new moments.  With two relaxation
+// times (TRT: the parts of f even and odd under c -> -c relax at w+ = 1/tau
+// and w- = 1/tau^-), a and b take w+, P takes w-, and the pulled term is
+// alpha g_i(s) + beta g_opp(i)(s), alpha = 1 - (w+ + w-)/2, beta =
+// (w- - w+)/2: the instance with TRT loads the opposite population of each
+// source as well.  The records are read
 // from LDS one whole 16-byte vector at a time: lanes 16 bytes apart reading
 // fewer values would share LDS banks.
 //
@@ -103,7 +108,7 @@ constexpr bool step_fits() { return sizeof(StepLds<T, BX, BY>) <= 160 * 1024; }
 #define LBM_FOR_SHAPES(M) M(32, 8) M(16, 16) M(16, 8) M(8, 16)
 
 
-template <typename T, typename S, int BX, int BY, int DG>
+template <typename T, typename S, int BX, int BY, int DG, bool TRT>
 __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
   using F = Frame<BX, BY>;
   constexpr int NT = F::NT, NW = F::NW, HX1 = F::HX1, N1 = F::N1, HX2 = F::HX2, N2 = F::N2;
@@ -159,10 +164,15 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
     // run parameters in registers: a load of them inside the z-march would
     // wait for every load in flight as well
     const T G = T(R.G);
-    const T tA = T(R.tau[0]), tB = T(R.tau[1]);
-    const T itA = T(R.inv_tau[0]), itB = T(R.inv_tau[1]);
-    const T om = s ? itB : itA;   // 1/tau of this thread's component
-    const T om1 = T(1) - om;
+    const T itA = T(R.inv_tau[0]), itB = T(R.inv_tau[1]);     // w+ (BGK: w)
+    // tau^- and w-: in the BGK instance every run has tau^- = tau
+    const T tmA = T(TRT ? R.tau_m[0] : R.tau[0]), tmB = T(TRT ? R.tau_m[1] : R.tau[1]);
+    const T itmA = TRT ? T(R.inv_tau_m[0]) : itA, itmB = TRT ? T(R.inv_tau_m[1]) : itB;
+    const T om = s ? itB : itA;   // w+ of this thread's component
+    const T omm = s ? itmB : itmA;
+    // weights of g_i(s) and g_opp(i)(s) in the collision (BGK: 1 - w, 0)
+    const T om1 = TRT ? T(1) - T(0.5) * (om + omm) : T(1) - om;
+    const T omb = T(0.5) * (omm - om);
     const T uw = T(R.u_wall);
     const int vph = R.visc;
     const T chi_lo = T(R.chi_lo), ichr = T(R.inv_chi_range), eP = T(R.etaP_over_tauP);
@@ -208,6 +218,7 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
     T cst[K2][6];    // C of the plane being staged, kept for the C ring
     T jv[6];         // momenta of the 1-frame position (plane to finalise)
     T pops[Q];       // populations arriving at the own column (plane to collide)
+    T popo[TRT ? Q : 1];   // with TRT: the opposite population of each source
     // values of the iteration's global stores: their registers are held to
     // the end of the iteration, so that none is overwritten while its store
     // may still be reading it (which would wait for the store to finish)
@@ -258,6 +269,18 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
           off = in ? off : (uint32_t)(OPPI[i] % DG) * db + ownb;
         }
         pops[i] = St::load(boff(src, off), 0);
+        if constexpr (TRT) {
+          // g_opp(i) at the source, or g_i of x itself across a wall
+          const S* srco = grp(fs, OPPI[i]);
+          uint32_t offo = (uint32_t)(OPPI[i] % DG) * db +
+                          ((uint32_t)zs * pb + rowb[1 - CY[i]] + colb[1 - CX[i]]);
+          if (CZ[i] != 0) {
+            const bool in = zs >= 0 && zs < nz;
+            srco = in ? srco : grp(fs, i);
+            offo = in ? offo : (uint32_t)(i % DG) * db + ownb;
+          }
+          popo[i] = St::load(boff(srco, offo), 0);
+        }
       }
     };
 
@@ -355,6 +378,7 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
           e = e + (T(3) * cP - k3[i]) + r1.w * cu * cu;
         }
         T h = om1 * pops[i] + (wgt<T>(i) * kS) * e;
+        if constexpr (TRT) h = h + omb * popo[i];
         if (CZ[i] != 0) h = h - wall;
         pops[i] = h;
         drho = i == 0 ? h : drho + h;
@@ -518,13 +542,13 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
         }
       }
       // velocity shift u' = sum(j_s/tau_s)/sum(rho_s/tau_s),
-      // u^eq_s = u' + tau_s F_s/rho_s
-      const T iden = rcpT(rA * itA + rB * itB);
-      const T qA = tA * rcpT(rA), qB = tB * rcpT(rB);
+      // u^eq_s = u' + tau_s F_s/rho_s, with the momentum's rate tau^-
+      const T iden = rcpT(rA * itmA + rB * itmB);
+      const T qA = tmA * rcpT(rA), qB = tmB * rcpT(rB);
       T ueA[3], ueB[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const T up = (jv[c] * itA + jv[3 + c] * itB) * iden;
+        const T up = (jv[c] * itmA + jv[3 + c] * itmB) * iden;
         ueA[c] = up + qA * FA[c];
         ueB[c] = up + qB * FB[c];
       }
@@ -533,14 +557,14 @@ __global__ void __launch_bounds__(2 * BX * BY) k_step(StepArgs<T, S> a) {
         for (int cp = 0; cp < 2; ++cp) {
           const T rs = cp ? rB : rA;
           const T* ue = cp ? ueB : ueA;
-          const T w = cp ? itB : itA;
-          const T wr = w * rs, w1 = T(1) - w;
+          const T w = cp ? itB : itA, wm = cp ? itmB : itmA;
+          const T wr = w * rs, wmr = wm * rs, wm1 = T(1) - wm;
           const T usq = ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2];
           V4<T> r0, r1;
           r0.x = rs - T(1.5) * wr * usq;
-          r0.y = wr * ue[0] + w1 * jv[3 * cp];
-          r0.z = wr * ue[1] + w1 * jv[3 * cp + 1];
-          r0.w = wr * ue[2] + w1 * jv[3 * cp + 2];
+          r0.y = wmr * ue[0] + wm1 * jv[3 * cp];
+          r0.z = wmr * ue[1] + wm1 * jv[3 * cp + 1];
+          r0.w = wmr * ue[2] + wm1 * jv[3 * cp + 2];
           r1.x = ue[0]; r1.y = ue[1]; r1.z = ue[2];
           r1.w = T(4.5) * wr;
           L.rec[sm][cp][0][e1] = r0;
@@ -708,8 +732,14 @@ bool step_shape_ok(int bx, int by, bool fp64) {
 template <typename T, typename S, int BX, int BY>
 void launch_step_shape(const StepArgs<T, S>& a, dim3 grid, hipStream_t st) {
   if constexpr (step_fits<BX, BY, T>()) {
-    if (a.wide) k_step<T, S, BX, BY, DG_WIDE><<<grid, dim3(BX, BY, 2), 0, st>>>(a);
-    else k_step<T, S, BX, BY, Q><<<grid, dim3(BX, BY, 2), 0, st>>>(a);
+    const dim3 blk(BX, BY, 2);
+    if (a.trt) {
+      if (a.wide) k_step<T, S, BX, BY, DG_WIDE, true><<<grid, blk, 0, st>>>(a);
+      else k_step<T, S, BX, BY, Q, true><<<grid, blk, 0, st>>>(a);
+    } else {
+      if (a.wide) k_step<T, S, BX, BY, DG_WIDE, false><<<grid, blk, 0, st>>>(a);
+      else k_step<T, S, BX, BY, Q, false><<<grid, blk, 0, st>>>(a);
+    }
   }
 }
 
@@ -724,7 +754,7 @@ void launch_step(const StepArgs<T, S>& a, dim3 grid, dim3 block, hipStream_t s) 
 
 // Workgroups of the step kernel that one CU holds at once (LDS, registers).
 template <typename T, typename S>
-int step_blocks_per_cu(int bx, int by, bool wide) {
+int step_blocks_per_cu(int bx, int by, bool wide, bool trt) {
   int n = 0;
   auto occ = [&](auto kern, int threads) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, threads, 0) != hipSuccess) n = 0;
@@ -732,8 +762,13 @@ int step_blocks_per_cu(int bx, int by, bool wide) {
 #define STEP_OCC(BX, BY)                                                            \
   if (bx == BX && by == BY) {                                                       \
     if constexpr (step_fits<BX, BY, T>()) {                                         \
-      if (wide) occ(k_step<T, S, BX, BY, DG_WIDE>, 2 * BX * BY);                     \
-      else occ(k_step<T, S, BX, BY, Q>, 2 * BX * BY);                                \
+      if (trt) {                                                                    \
+        if (wide) occ(k_step<T, S, BX, BY, DG_WIDE, true>, 2 * BX * BY);            \
+        else occ(k_step<T, S, BX, BY, Q, true>, 2 * BX * BY);                       \
+      } else {                                                                      \
+        if (wide) occ(k_step<T, S, BX, BY, DG_WIDE, false>, 2 * BX * BY);           \
+        else occ(k_step<T, S, BX, BY, Q, false>, 2 * BX * BY);                      \
+      }                                                                             \
     }                                                                               \
   }
   LBM_FOR_SHAPES(STEP_OCC)
@@ -748,7 +783,7 @@ void launch_flow(const AuxArgs<T, S>& a, hipStream_t s) {
 
 #define LBM_INST(T, S)                                                                  \
   template void launch_step<T, S>(const StepArgs<T, S>&, dim3, dim3, hipStream_t);     \
-  template int step_blocks_per_cu<T, S>(int, int, bool);                                \
+  template int step_blocks_per_cu<T, S>(int, int, bool, bool);                          \
   template void launch_flow<T, S>(const AuxArgs<T, S>&, hipStream_t);
 LBM_INST(double, double)
 LBM_INST(float, float)

@@ -43,6 +43,7 @@ class LbmParams(ctypes.Structure):
         ("L2", ctypes.c_double * 2),
         ("chi_lo", ctypes.c_double), ("chi_hi", ctypes.c_double),
         ("seed", ctypes.c_uint64), ("init_noise", ctypes.c_double),
+        ("tau_minus", ctypes.c_double * 2),
     ]
 
 
@@ -178,6 +179,8 @@ def make_params(d: dict, precision: str = "fp64") -> LbmParams:
     p.chi_hi = float(d.get("chi_hi", 0.0))
     p.seed = int(d.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
     p.init_noise = float(d.get("init_noise", 0.0))
+    tm = d.get("tau_minus") or (0.0, 0.0)
+    p.tau_minus[0], p.tau_minus[1] = float(tm[0]), float(tm[1])
     return p
 
 

@@ -106,7 +106,7 @@ def lattice(spec: RunSpec):
 
 def simulate(specs, precision: str = "fp32", t_end: int | None = None, every: int = 1000,
              min_steps: int = 4000, max_steps: int = 40000, device="cuda:0", launch=None,
-             progress=None, extend_to: int = 0, grow_window: int = 4000):
+             progress=None, extend_to: int = 0, grow_window: int = 4000, prepared=None):
     """Advance every run (one batch) to its end time, checking for break-up
     every ``every`` steps; a broken run is stopped (masked) at once.  With
     ``extend_to`` > 0, a run still whole at its end time whose droplet is
@@ -114,10 +114,12 @@ def simulate(specs, precision: str = "fp32", t_end: int | None = None, every: in
     check by check, until it breaks, stops elongating or reaches
     ``extend_to`` steps.  Steady D and orientation are averaged over the last
     three checks of unbroken runs; ``progress`` (a callable) receives a line
-    after every check.  Returns (results, seconds)."""
+    after every check.  ``prepared`` (a list of (params, info), one per
+    spec) replaces the study window's mapping of the specs to lattice
+    parameters.  Returns (results, seconds)."""
     results, runs = [], []
-    for sp in specs:
-        p, info = lattice(sp)
+    for k, sp in enumerate(specs):
+        p, info = prepared[k] if prepared is not None else lattice(sp)
         results.append(RunResult(sp, p, info))
         runs.append(p)
     ends = []

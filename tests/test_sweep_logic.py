@@ -273,3 +273,24 @@ def test_modes_report_maps_each_mode(monkeypatch, tmp_path):
         assert r["u_wall"] <= sweep.U_MAX * (1 + 1e-9)
         assert tB == pytest.approx(study.MODE_TAU_MATRIX[r["mode"]])   # the matrix is B
         assert r["Lp_max_over_2R"] == pytest.approx(1.0)
+
+
+def test_paper_scale_mapping_and_bracket():
+    """Host logic of the paper-scale Ca_cr driver: lambda on the total
+    viscosities with the polymer fraction in the right phase, the wall speed
+    from Ca, and the bracket from a scan."""
+    from paper_1411_2181_amd import paper_scale as P
+    eta = P.eta_of(6.0)
+    assert abs(P.eta_of(P.tau_of(0.7)) - 0.7) < 1e-15
+    ta, tb, ea, eb = P.viscosities("DV", eta, 1.0, 0.4)
+    assert tb == 6.0 and eb == 0.0 and abs(P.eta_of(ta) + ea - eta) < 1e-12
+    ta, tb, ea, eb = P.viscosities("MV", eta, 1.0, 0.4)
+    assert ta == 6.0 and ea == 0.0 and abs(P.eta_of(tb) + eb - eta) < 1e-12
+    p, info = P.run_params("N", 0.3, 32.0, 0.52, 2.0, 1.0, 0.4, 100.0, eta, 1.0, 0.14, 0.75, 0.19)
+    assert p["nz"] == 123 and p["tau_minus"] == (1.0, 1.0)
+    assert abs(p["u_wall"] - 0.3 * 0.14 / (eta * 32.0) * 123 / 2.0) < 1e-15
+    rows = [dict(Ca=0.3, broken=False, status=0), dict(Ca=0.34, broken=False, status=0),
+            dict(Ca=0.38, broken=True, status=0), dict(Ca=0.42, broken=True, status=0)]
+    assert P.bracket(rows) == (0.34, 0.38)
+    assert P.bracket(rows[:2]) == (0.34, None)
+    assert P.bracket(rows[2:]) == (None, 0.38)
