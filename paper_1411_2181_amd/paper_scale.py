@@ -19,8 +19,12 @@ Stages, all on the GPU through the batched solver:
      (the paper's last snapshot is at t/tau_em = 100), checked for break-up
      every --every steps by connected-component labelling; a broken run is
      masked at once;
-  3. per mode, the bracket [largest Ca that stayed whole below the smallest
-     that broke, that smallest], with the Reynolds number at the bracket.
+  3. per mode, two brackets with the Reynolds number at each: by break-up
+     ([largest Ca that stayed whole below the smallest that broke, that
+     smallest]) and by the shape criterion of the paper's figures, which
+     tell sub-critical droplets (a steady shape) from super-critical ones
+     (still stretching, or broken): a run is steady when its length L_p
+     changed by less than STEADY_TOL over its last STEADY_TEM tau_em.
 
     python -m paper_1411_2181_amd.paper_scale OUT.json --R 32 --c 0.52 --tau-plus 6 \\
         --tau-minus 1 --De 2 --N 0.28,0.32,0.36 --DV 0.36,0.4 --MV 0.28,0.32
@@ -41,6 +45,7 @@ RHO_REF = physics.RHO_MAJOR + physics.RHO_MINOR
 # box of the paper's runs in units of R: 1024 x 128 x W at R = 50
 BOX_X, BOX_Y = 1024.0 / 50.0, 128.0 / 50.0
 T_TEM = 100.0
+STEADY_TEM, STEADY_TOL = 10.0, 0.02
 
 
 def eta_of(tau_plus: float) -> float:
@@ -115,15 +120,44 @@ def run_params(mode, Ca, R, c, De, lam, fraction, L2, eta_M, tau_minus, sigma, G
     return p, info
 
 
-def bracket(rows):
-    """[largest whole Ca below the smallest broken Ca, that Ca] (None where
-    no run of that kind exists)."""
-    broken = sorted(r["Ca"] for r in rows if r["broken"])
-    hi = broken[0] if broken else None
-    whole = [r["Ca"] for r in rows if not r["broken"] and r["status"] == 0
-             and (hi is None or r["Ca"] < hi)]
-    lo = max(whole) if whole else None
+def bracket(rows, key="broken"):
+    """[largest Ca below the smallest Ca with row[key] true among the runs
+    with it false (status 0), that Ca] (None where no run of that kind
+    exists)."""
+    hit = sorted(r["Ca"] for r in rows if r[key])
+    hi = hit[0] if hit else None
+    miss = [r["Ca"] for r in rows if not r[key] and r["status"] == 0
+            and (hi is None or r["Ca"] < hi)]
+    lo = max(miss) if miss else None
     return lo, hi
+
+
+def steady(history, tau_em: float, window_tem: float = STEADY_TEM, tol: float = STEADY_TOL) -> bool:
+    """L_p at the last check within tol (relative) of L_p at the last check
+    at least window_tem tau_em earlier."""
+    if not history:
+        return False
+    t1, lp1 = history[-1]["step"], history[-1]["Lp_over_2R"]
+    earlier = [h for h in history if h["step"] <= t1 - window_tem * tau_em]
+    if not earlier:
+        return False
+    lp0 = earlier[-1]["Lp_over_2R"]
+    return abs(lp1 - lp0) <= tol * lp0
+
+
+def brackets_of(rows, modes):
+    """Per mode: the break-up bracket and the shape bracket (super-critical =
+    broken or still stretching), each with Re at its ends."""
+    out = {}
+    for mode in modes:
+        rs = [dict(r, supercritical=r["broken"] or not r["steady"]) for r in rows if r["mode"] == mode]
+        entry = {}
+        for name, key in (("breakup", "broken"), ("shape", "supercritical")):
+            lo, hi = bracket(rs, key)
+            re_at = [r["Re"] for r in rs if r["Ca"] in (lo, hi)]
+            entry[name] = dict(Ca_cr_lo=lo, Ca_cr_hi=hi, Re=[min(re_at), max(re_at)] if re_at else None)
+        out[mode] = entry
+    return out
 
 
 def main(argv=None):
@@ -146,10 +180,26 @@ def main(argv=None):
     ap.add_argument("--u-max", type=float, default=0.19)
     ap.add_argument("--sigma-steps", type=int, default=calibrate.STEPS)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16s"])
+    ap.add_argument("--combine", default="",
+                    help="A.json,B.json: merge the rows of earlier scans (same set-up) into OUT")
     args = ap.parse_args(argv)
 
     def log(msg):
         print(msg, flush=True)
+
+    if args.combine:
+        scans = [json.load(open(p)) for p in args.combine.split(",")]
+        rows = sorted((r for s in scans for r in s["rows"]), key=lambda r: (r["mode"], r["Ca"]))
+        modes = [m for m in ("N", "DV", "MV") if any(r["mode"] == m for r in rows)]
+        out = {k: v for k, v in scans[0].items() if k not in ("rows", "brackets", "seconds", "seconds_runs")}
+        out.update(scans=args.combine.split(","), brackets=brackets_of(rows, modes),
+                   sigma={m: [s["sigma"][m] for s in scans if m in s.get("sigma", {})] for m in modes},
+                   rows=rows)
+        for m in modes:
+            log(f"{m}: {out['brackets'][m]}")
+        with open(args.out, "w") as fh:
+            json.dump(out, fh, indent=1, default=float)
+        return 0
 
     t0 = time.perf_counter()
     eta_M = eta_of(args.tau_plus)
@@ -178,6 +228,7 @@ def main(argv=None):
         hist = [dict(step=h[0], t_over_tau_em=h[0] / tem, D=h[1], theta=h[2],
                      Lp_over_2R=h[3] / (2 * args.R), pieces=h[4]) for h in r.history]
         rows.append(dict(t, tau_plus=list(r.params["tau"]), tau_minus=args.tau_minus,
+                         steady=steady(hist, tem),
                          u_wall=r.params["u_wall"], tau_P=r.params["tau_P"][0], Re=r.info["Re"],
                          tau_em=tem, broken=r.broken, step_break=r.step_break, status=r.status,
                          steps=r.steps, t_break_over_tau_em=(r.step_break / tem) if r.broken else None,
@@ -187,18 +238,15 @@ def main(argv=None):
             + (f"breaks at t/tau_em = {r.step_break / tem:.1f} into {len(r.pieces)} {r.pieces}"
                if r.broken else f"whole after {r.steps} steps (status {r.status})")
             + f", max Lp/2R {rows[-1]['Lp_max_over_2R']:.2f}")
-    brackets = {}
-    for (mode, _cas), (sigma, resid) in zip(modes, sig):
-        lo, hi = bracket([r for r in rows if r["mode"] == mode])
-        re_at = [r["Re"] for r in rows if r["mode"] == mode and r["Ca"] in (lo, hi)]
-        brackets[mode] = dict(Ca_cr_lo=lo, Ca_cr_hi=hi, sigma=sigma, laplace_residual=resid,
-                              Re=[min(re_at), max(re_at)] if re_at else None)
-        log(f"{mode}: Ca_cr in ({lo}, {hi}]")
+    brackets = brackets_of(rows, [m for m, _ in modes])
+    sigmas = {m: dict(sigma=s, laplace_residual=res) for (m, _), (s, res) in zip(modes, sig)}
+    for m, _ in modes:
+        log(f"{m}: {brackets[m]}")
     out = dict(R=args.R, c=args.c, tau_plus_matrix=args.tau_plus, tau_minus=args.tau_minus,
                eta_M=eta_M, G=args.G, De=args.De, lam=args.lam, fraction=args.fraction, L2=args.L2,
                precision=args.precision, t_over_tau_em=args.t_tem, t_end=t_end, every=args.every,
                box=prepared[0][1]["box"], nodes_total=nodes, seconds=time.perf_counter() - t0,
-               seconds_runs=sec, brackets=brackets, rows=rows)
+               seconds_runs=sec, sigma=sigmas, brackets=brackets, rows=rows)
     with open(args.out, "w") as fh:
         json.dump(out, fh, indent=1, default=float)
     return 0
