@@ -79,9 +79,12 @@ def sigma_runs(taus, tau_minus: float, G: float):
     return runs
 
 
-def measure_sigma(taus, tau_minus: float, G: float, precision: str, steps: int, log=print):
+def measure_sigma(taus, tau_minus: float, G: float, precision: str, steps: int, log=print,
+                  densities=None):
     """sigma (least squares of dp = 2 sigma / R_eff over the three radii) and
-    the largest relative residual, per (tau^+_A, tau^+_B) pair."""
+    the largest relative residual, per (tau^+_A, tau^+_B) pair (tau_minus = 0:
+    BGK).  ``densities`` (a list) receives the component densities at the
+    centre and in the far matrix of the middle radius's droplet."""
     runs = sigma_runs(taus, tau_minus, G)
     b = lbmve.Batch(runs, precision)
     b.step([steps] * len(runs))
@@ -90,9 +93,14 @@ def measure_sigma(taus, tau_minus: float, G: float, precision: str, steps: int, 
     for k, pair in enumerate(taus):
         x, y = [], []
         for j in range(nr):
-            dp, reff = calibrate.laplace_measure(b.export("rho", k * nr + j), G)
+            rho = b.export("rho", k * nr + j)
+            dp, reff = calibrate.laplace_measure(rho, G)
             x.append(1.0 / reff)
             y.append(dp)
+            if densities is not None and j == nr // 2:
+                c = calibrate.BOX // 2
+                densities.append(dict(A_in=float(rho[0][c, c, c]), B_in=float(rho[1][c, c, c]),
+                                      A_out=float(rho[0][c, 1, 1]), B_out=float(rho[1][c, 1, 1])))
         x, y = np.array(x), np.array(y)
         sig = float(x @ y / (x @ x) / 2.0)
         resid = float(np.abs(y - 2.0 * sig * x).max() / np.abs(y).max())
@@ -182,10 +190,26 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16s"])
     ap.add_argument("--combine", default="",
                     help="A.json,B.json: merge the rows of earlier scans (same set-up) into OUT")
+    ap.add_argument("--window", default="",
+                    help="'tA,tB;tA,tB;...': only the static-droplet stage, for these tau^+ pairs, "
+                         "with BGK (tau = tau^+) and with --tau-minus")
     args = ap.parse_args(argv)
 
     def log(msg):
         print(msg, flush=True)
+
+    if args.window:
+        pairs = [tuple(float(v) for v in p.split(",")) for p in args.window.split(";")]
+        res = {}
+        for name, tm in (("bgk", 0.0), (f"trt tau_minus={args.tau_minus}", args.tau_minus)):
+            dens = []
+            sig = measure_sigma(pairs, tm, args.G, args.precision, args.sigma_steps, log, dens)
+            res[name] = [dict(tau_plus=list(p), sigma=s, laplace_residual=r, densities_R12=d)
+                         for p, (s, r), d in zip(pairs, sig, dens)]
+        with open(args.out, "w") as fh:
+            json.dump(dict(G=args.G, steps=args.sigma_steps, radii=list(calibrate.RADII),
+                           box=calibrate.BOX, precision=args.precision, window=res), fh, indent=1)
+        return 0
 
     if args.combine:
         scans = [json.load(open(p)) for p in args.combine.split(",")]
