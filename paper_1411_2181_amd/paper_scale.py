@@ -110,9 +110,10 @@ def measure_sigma(taus, tau_minus: float, G: float, precision: str, steps: int, 
     return out
 
 
-def run_params(mode, Ca, R, c, De, lam, fraction, L2, eta_M, tau_minus, sigma, G, u_max):
+def run_params(mode, Ca, R, c, De, lam, fraction, L2, eta_M, tau_minus, sigma, G, u_max,
+               box_x=BOX_X):
     W = int(round(2.0 * R / c))
-    nx, ny = int(round(BOX_X * R)), int(round(BOX_Y * R))
+    nx, ny = int(round(box_x * R)), int(round(BOX_Y * R))
     ta, tb, ePA, ePB = viscosities(mode, eta_M, lam, fraction)
     gdot = Ca * sigma / (eta_M * R)
     u_wall = gdot * W / 2.0
@@ -184,6 +185,7 @@ def main(argv=None):
     ap.add_argument("--DV", default="", help="Ca list, polymer in the droplet")
     ap.add_argument("--MV", default="", help="Ca list, polymer in the matrix")
     ap.add_argument("--t-tem", type=float, default=T_TEM, help="run length in tau_em")
+    ap.add_argument("--box-x", type=float, default=BOX_X, help="box length in units of R")
     ap.add_argument("--every", type=int, default=2000)
     ap.add_argument("--u-max", type=float, default=0.19)
     ap.add_argument("--sigma-steps", type=int, default=calibrate.STEPS)
@@ -235,7 +237,8 @@ def main(argv=None):
     for (mode, cas), (sigma, _res) in zip(modes, sig):
         for ca in cas:
             p, info = run_params(mode, ca, args.R, args.c, args.De, args.lam, args.fraction,
-                                 args.L2, eta_M, args.tau_minus, sigma, args.G, args.u_max)
+                                 args.L2, eta_M, args.tau_minus, sigma, args.G, args.u_max,
+                                 box_x=args.box_x)
             specs.append(sweep.RunSpec(args.R, args.c, ca, args.De if mode != "N" else 0.0,
                                        args.lam, args.L2, args.fraction, phase=mode))
             prepared.append((p, info))
