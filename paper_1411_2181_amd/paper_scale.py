@@ -253,7 +253,9 @@ def main(argv=None):
     for t, r in zip(tags, res):
         tem = r.info["tau_em"]
         hist = [dict(step=h[0], t_over_tau_em=h[0] / tem, D=h[1], theta=h[2],
-                     Lp_over_2R=h[3] / (2 * args.R), pieces=h[4]) for h in r.history]
+                     Lp_over_2R=h[3] / (2 * args.R), pieces=h[4],
+                     volume_over_initial=h[5] / (4.0 / 3.0 * math.pi * args.R ** 3))
+                for h in r.history]
         rows.append(dict(t, tau_plus=list(r.params["tau"]), tau_minus=args.tau_minus,
                          steady=steady(hist, tem),
                          u_wall=r.params["u_wall"], tau_P=r.params["tau_P"][0], Re=r.info["Re"],

@@ -143,7 +143,9 @@ def simulate(specs, precision: str = "fp32", t_end: int | None = None, every: in
             remaining[k] -= chunk[k]
             r.steps = o["step"]
             r.status = o["status"]
-            r.history.append((o["step"], o["D"], o["theta_deg"], o["Lp"], o["n_components"]))
+            # (step, D, theta, L_p, pieces, nodes of the four largest pieces)
+            r.history.append((o["step"], o["D"], o["theta_deg"], o["Lp"], o["n_components"],
+                              sum(o["piece_nodes"])))
             r.Lp_max = max(r.Lp_max, o["Lp"])
             if o["status"] != 0:
                 remaining[k] = 0
