@@ -55,6 +55,7 @@ def scalar_step(f, Cf, prm):
     Returns new (f, C) as nested Python lists."""
     nx, ny, nz = prm.nx, prm.ny, prm.nz
     tau = prm.tau
+    tau_m = prm.tau_minus   # odd-moment times (equal to tau under BGK)
     G = prm.G
     ph = prm.phase
 
@@ -134,16 +135,27 @@ def scalar_step(f, Cf, prm):
                 FA, FB = force_at(x, y, z)
                 rA, rB = rho[0][z][y][x], rho[1][z][y][x]
                 jA, jB = jm[0][z][y][x], jm[1][z][y][x]
-                den = rA / tau[0] + rB / tau[1]
-                up = [(jA[a] / tau[0] + jB[a] / tau[1]) / den for a in range(3)]
-                ueq[0][z][y][x] = [up[a] + tau[0] * FA[a] / rA for a in range(3)]
-                ueq[1][z][y][x] = [up[a] + tau[1] * FB[a] / rB for a in range(3)]
+                for a in range(3):
+                    FA[a] += rA * prm.body_accel[a]
+                    FB[a] += rB * prm.body_accel[a]
+                den = rA / tau_m[0] + rB / tau_m[1]
+                up = [(jA[a] / tau_m[0] + jB[a] / tau_m[1]) / den for a in range(3)]
+                ueq[0][z][y][x] = [up[a] + tau_m[0] * FA[a] / rA for a in range(3)]
+                ueq[1][z][y][x] = [up[a] + tau_m[1] * FB[a] / rB for a in range(3)]
                 uph[z][y][x] = [(jA[a] + jB[a] + 0.5 * (FA[a] + FB[a])) / (rA + rB)
                                 for a in range(3)]
 
     def post(s, i, x, y, z):
         fv = float(f[s][i][z][y][x])
-        return fv - (fv - _feq(i, rho[s][z][y][x], ueq[s][z][y][x])) / tau[s]
+        r, u = rho[s][z][y][x], ueq[s][z][y][x]
+        if tau_m[s] == tau[s]:
+            return fv - (fv - _feq(i, r, u)) / tau[s]
+        # two relaxation times: the parts even and odd under i -> opposite(i)
+        o = OPPOSITE[i]
+        fo = float(f[s][o][z][y][x])
+        even = 0.5 * (fv + fo) - 0.5 * (_feq(i, r, u) + _feq(o, r, u))
+        odd = 0.5 * (fv - fo) - 0.5 * (_feq(i, r, u) - _feq(o, r, u))
+        return fv - even / tau[s] - odd / tau_m[s]
 
     fn = [[[[[0.0] * nx for _ in range(ny)] for _ in range(nz)] for _ in range(19)]
           for _ in range(2)]

@@ -141,3 +141,14 @@ def test_init_noise_amplitude_is_validated(L):
                   (float("nan"), False)):
         p = lbmve.make_params(dict(d, seed=2**64 - 1, init_noise=a), "fp64")
         assert (L.lbm_validate(ctypes.byref(p)) == 0) == ok, a
+
+
+def test_tau_minus_is_validated(L):
+    """The odd-moment relaxation time is 0 (BGK) or a finite value above 1/2."""
+    from paper_1411_2181_amd import lbmve
+    d = WL.small_droplet_viscoelastic()
+    for tm, ok in (((0.0, 0.0), True), ((1.25, 0.0), True), ((0.51, 3.0), True),
+                   ((0.5, 1.0), False), ((1.0, -1.0), False), ((float("nan"), 1.0), False),
+                   ((1.0, float("inf")), False)):
+        p = lbmve.make_params(dict(d, tau_minus=tm), "fp32")
+        assert (L.lbm_validate(ctypes.byref(p)) == 0) == ok, tm

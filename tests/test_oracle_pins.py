@@ -152,9 +152,12 @@ def test_collision_conserves_mass_and_momentum_identity():
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("shape_xyz", [(3, 4, 5), (6, 5, 7)])
 @pytest.mark.parametrize("visc", [True, False])
-def test_vectorised_matches_brute_force(shape_xyz, visc):
+@pytest.mark.parametrize("trt", [False, True])
+def test_vectorised_matches_brute_force(shape_xyz, visc, trt):
     nx, ny, nz = shape_xyz
     p, f, C = _random_state((nz, ny, nx), 11, visc)
+    if trt:
+        p = dict(p, tau_minus=(0.7, 1.9))
     o = Oracle(p, f=f, C=C)
     prm = Params(p)
     fs, Cs = f.copy(), C.copy()
