@@ -294,3 +294,22 @@ def test_paper_scale_mapping_and_bracket():
     assert P.bracket(rows) == (0.34, 0.38)
     assert P.bracket(rows[:2]) == (0.34, None)
     assert P.bracket(rows[2:]) == (None, 0.38)
+
+
+def test_paper_scale_shape_criterion():
+    """A run is steady when L_p moved by at most 2 % over the last 10 tau_em;
+    the shape bracket counts broken or still-stretching runs as
+    super-critical."""
+    from paper_1411_2181_amd import paper_scale as P
+    tem = 100.0
+    flat = [dict(step=s, Lp_over_2R=v) for s, v in ((0, 1.0), (500, 1.70), (1000, 1.75), (1500, 1.76))]
+    grow = [dict(step=s, Lp_over_2R=v) for s, v in ((0, 1.0), (500, 1.5), (1000, 2.0), (1500, 2.5))]
+    assert P.steady(flat, tem) and not P.steady(grow, tem)
+    assert not P.steady(flat[:1], tem)            # no check a window earlier
+    rows = [dict(mode="N", Ca=0.3, broken=False, steady=True, status=0, Re=0.4),
+            dict(mode="N", Ca=0.34, broken=False, steady=False, status=0, Re=0.45),
+            dict(mode="N", Ca=0.38, broken=True, steady=False, status=0, Re=0.5)]
+    b = P.brackets_of(rows, ["N"])["N"]
+    assert (b["breakup"]["Ca_cr_lo"], b["breakup"]["Ca_cr_hi"]) == (0.34, 0.38)
+    assert (b["shape"]["Ca_cr_lo"], b["shape"]["Ca_cr_hi"]) == (0.3, 0.34)
+    assert b["shape"]["Re"] == [0.4, 0.45]
