@@ -302,7 +302,7 @@ def test_paper_scale_shape_criterion():
     super-critical."""
     from paper_1411_2181_amd import paper_scale as P
     tem = 100.0
-    flat = [dict(step=s, Lp_over_2R=v) for s, v in ((0, 1.0), (500, 1.70), (1000, 1.75), (1500, 1.76))]
+    flat = [dict(step=s, Lp_over_2R=v) for s, v in ((0, 1.0), (500, 1.74), (1000, 1.75), (1500, 1.76))]
     grow = [dict(step=s, Lp_over_2R=v) for s, v in ((0, 1.0), (500, 1.5), (1000, 2.0), (1500, 2.5))]
     assert P.steady(flat, tem) and not P.steady(grow, tem)
     assert not P.steady(flat[:1], tem)            # no check a window earlier
