@@ -88,8 +88,10 @@ def measured_traffic(precision, launch, box=BOX):
         return None
     if tuple(entry.get("box", BOX)) != tuple(box):
         return None
-    # a persistent grid over the same tiles is taken to move the same bytes
-    return entry["launches"].get(f"{launch['bx']}x{launch['by']}x{launch['bz']}")
+    # a persistent grid over the same tiles is taken to move the same bytes;
+    # bz = 0 (whole columns) is the same tile table as bz = nz
+    bz = launch["bz"] if launch["bz"] > 0 else box[2]
+    return entry["launches"].get(f"{launch['bx']}x{launch['by']}x{bz}")
 
 
 def gpu_run(precision, steps, warmup, launch=None, box=BOX, tau_minus=None):

@@ -31,7 +31,7 @@ from collections import defaultdict
 from .build import source_hash
 
 COPY_BYTES = 1 << 30
-_STEP = re.compile(r"lbm::k_(step)<[^,]+, [^,]+, (\d+), (\d+)(?:, \d+)?>")
+_STEP = re.compile(r"lbm::k_(step)<[^,]+, [^,]+, (\d+), (\d+)(?:, \w+)*>")
 
 
 def _launch(kind, bx, by, grid_items, wg_items, box):
