@@ -313,3 +313,25 @@ def test_paper_scale_shape_criterion():
     assert (b["breakup"]["Ca_cr_lo"], b["breakup"]["Ca_cr_hi"]) == (0.34, 0.38)
     assert (b["shape"]["Ca_cr_lo"], b["shape"]["Ca_cr_hi"]) == (0.3, 0.34)
     assert b["shape"]["Re"] == [0.4, 0.45]
+
+
+def test_paper_scale_combines_scans(tmp_path):
+    """--combine merges the rows of several scans of one set-up and brackets
+    them together (here: a stable and a broken Ca from two scans)."""
+    import json
+    from paper_1411_2181_amd import paper_scale as P
+    base = dict(R=32.0, c=0.52, tau_plus_matrix=6.0, tau_minus=1.25, seconds=1.0)
+    hist = [dict(step=s, Lp_over_2R=2.0) for s in (0, 2000, 4000)]
+    a = dict(base, sigma={"N": dict(sigma=0.16, laplace_residual=0.005)},
+             rows=[dict(mode="N", Ca=0.30, broken=False, steady=True, status=0, Re=0.43, history=hist)])
+    b = dict(base, sigma={"N": dict(sigma=0.16, laplace_residual=0.005)},
+             rows=[dict(mode="N", Ca=0.34, broken=True, steady=False, status=0, Re=0.48, history=hist)])
+    pa, pb, out = tmp_path / "a.json", tmp_path / "b.json", tmp_path / "out.json"
+    pa.write_text(json.dumps(a))
+    pb.write_text(json.dumps(b))
+    assert P.main([str(out), "--combine", f"{pa},{pb}"]) == 0
+    d = json.loads(out.read_text())
+    assert [r["Ca"] for r in d["rows"]] == [0.30, 0.34]
+    br = d["brackets"]["N"]["breakup"]
+    assert (br["Ca_cr_lo"], br["Ca_cr_hi"], br["Re"]) == (0.30, 0.34, [0.43, 0.48])
+    assert "seconds" not in d and d["tau_minus"] == 1.25
